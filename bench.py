@@ -1,0 +1,169 @@
+"""Throughput of the batched Gerchberg extension + Fourier reconstruction on one MI355X.
+
+Workload: 4096 independent 40x40 Shack-Hartmann frames (SPHERE-like geometry,
+von Karman screens D = 8 m, r0 = 0.15 m, L0 = 25 m, slope noise 0.05 rad),
+padded to 80x80, 10 Gerchberg iterations, Eq. 5 after the loop, MMSE final
+filter; float32 slopes in, float32 phase out, one launch per step.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1705_04298_amd import inputs as I  # noqa: E402
+
+N_SUB, N_GRID, N_ITER, BATCH = 40, 80, 10, 4096
+FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector peak [flop/s]
+
+
+def algorithmic_flops_per_frame(N: int, n_iter: int) -> float:
+    """Per-frame work of the paper's formulation (Eq. 8 made concrete): two complex
+    N^2-point FFTs per iteration and for the final step at 5 M log2 M flops each,
+    ~24 flop per frequency for the in-loop filter and gradient, ~16 for the final one."""
+    M = N * N
+    fft = 5.0 * M * math.log2(M)
+    return n_iter * (2 * fft + 24 * M) + (2 * fft + 16 * M)
+
+
+def _gen(args):
+    start, count = args
+    return I.make_batch(I.SPHERE_40_BATCH, count, start=start, dtype=np.float32)
+
+
+def make_inputs(B: int, workers: int) -> np.ndarray:
+    chunk = 64
+    jobs = [(s, min(chunk, B - s)) for s in range(0, B, chunk)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_gen, jobs)
+    return np.concatenate(parts, axis=0)
+
+
+_CPU_SLOPES = None
+
+
+def _oracle_frames(idx):
+    from oracle import fwr_oracle as O
+    p = O.Params(n_sub=N_SUB, n_grid=N_GRID, n_iter=N_ITER, periodic=True, gamma=1.0,
+                 noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=0.2)
+    mask = I.pupil_mask(N_SUB)
+    for i in idx:
+        O.reconstruct(_CPU_SLOPES[i].astype(np.float64), mask, p)
+    return len(idx)
+
+
+def cpu_baseline(slopes: np.ndarray, workers: int, sample: int) -> dict:
+    """The FP64 oracle, unchanged, over `sample` frames split across `workers` processes."""
+    global _CPU_SLOPES
+    _CPU_SLOPES = slopes
+    idx = np.arange(sample)
+    parts = [idx[w::workers] for w in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_frames, parts))
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {sample} frames of the benchmark batch, FP64 NumPy oracle, "
+                      f"{workers} single-threaded worker processes, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=BATCH)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (frames are independent; see the design notes "
+              f"for how the batch shards): --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    slopes = make_inputs(args.batch, workers)
+    print(f"[bench] generated {args.batch} frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(slopes, workers, min(args.cpu_sample, args.batch))
+        print(f"[bench] cpu baseline {cpu['value']:.0f} frames/s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1705_04298_amd import fwr
+
+    torch.cuda.set_device(0)
+    mask = I.pupil_mask(N_SUB)
+    plan = fwr.Plan(N_SUB, N_GRID, mask, n_iter=N_ITER, periodic=True, gamma=1.0,
+                    noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=0.2, max_batch=args.batch)
+    threads, fpg, lds = plan.launch_info()
+    x = torch.from_numpy(slopes).cuda()
+    out = torch.empty((args.batch, N_SUB + 1, N_SUB + 1), device="cuda", dtype=torch.float32)
+    for _ in range(args.warmup):
+        plan.reconstruct(x, out)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t_begin = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_begin.record()
+    for k in range(args.steps):
+        starts[k].record()
+        plan.reconstruct(x, out)
+        ends[k].record()
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_begin.elapsed_time(t_end)
+    per_launch_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = total_ms / args.steps
+    frames_per_s = args.batch * args.steps / (total_ms / 1e3)
+
+    flops = algorithmic_flops_per_frame(N_GRID, N_ITER) * args.batch
+    achieved = flops / (per_launch_ms / 1e3)
+    line = {
+        "metric": "frames/s (40x40 SH, 10 Gerchberg iters) + rms phase err vs FP64 oracle",
+        "value": frames_per_s,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096 frames 40x40 SH (Fried), pupil 14% obstruction, padded 80x80, "
+                               "10 Gerchberg iterations + Eq.5 + MMSE, von Karman D=8m r0=0.15m L0=25m, "
+                               "noise 0.05 rad",
+                   "batch": args.batch, "n_sub": N_SUB, "n_grid": N_GRID, "n_iter": N_ITER,
+                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                     "kernel_ms": per_launch_ms,
+                     "flops_per_frame": algorithmic_flops_per_frame(N_GRID, N_ITER)},
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

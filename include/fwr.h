@@ -1,0 +1,127 @@
+/*
+ * fwr.h -- C ABI of libfwr: Gerchberg slope extension and Fourier wave-front
+ * reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bond et al., "Iterative wave-front reconstruction in the Fourier
+ * domain".  The library computes, per frame of Shack-Hartmann slopes:
+ *   - the padded measurement: in-pupil slopes placed centred on an N x N grid,
+ *     zeros elsewhere (Sec. 4.1: zero iterations = zero padding);
+ *   - n_iter iterations of the modified Gerchberg loop (Sec. 3.3,
+ *     Algorithm 1 steps 1-4): transform, least-squares phase reconstruction
+ *     followed by re-derivation of the slopes (Eq. 2 and Eq. 3 with
+ *     gamma = 0), inverse transform, re-imposition of the measured slopes
+ *     inside the pupil;
+ *   - optionally the periodicity condition of Eq. 5 (Algorithm 1 step 5);
+ *   - the final Fourier reconstruction of Eq. 2 with the Wiener filter of
+ *     Eq. 3 (gamma = 1 gives the MMSE filter; gamma = 0 least squares).
+ * The slope model is the Fried geometry: a subaperture measures the mean of
+ * the two phase differences across its four corner nodes (the discrete model
+ * of Eq. 1; the paper's own sub-pixel filter is not reproduced).
+ *
+ * Conventions (all calls):
+ *   - Row index = y, column index = x, row-major, float32, no padding.
+ *   - Lenslet array n x n; grid N x N with N > n, N - n even; the array sits
+ *     at offset o = (N - n) / 2 in both axes.
+ *   - Slopes in:  float[B][2][n][n]  (plane 0 = x slopes, plane 1 = y), radians
+ *     of phase difference across one subaperture.  Values on subapertures the
+ *     mask marks invalid are ignored.
+ *   - Phase out:  float[B][n+1][n+1]  on the Fried nodes of the lenslet array
+ *     (grid nodes [o, o+n] x [o, o+n]); radians; the mean over the full N x N
+ *     grid is zero.
+ *   - Extended slopes out: float[B][2][N][N].
+ *   - Every pointer argument of fwr_extend / fwr_reconstruct is a DEVICE
+ *     pointer on the device the plan was created on.  The caller owns every
+ *     input and output buffer and keeps it alive until the plan's stream has
+ *     passed the enqueued work.
+ *   - Calls are asynchronous: they validate, enqueue on the plan's stream and
+ *     return.  Errors are reported only through the status code; nothing is
+ *     thrown across this boundary.  A kernel fault surfaces as FWR_E_DEVICE
+ *     from a later call or from the caller's own stream synchronisation.
+ *   - One plan may be used from one host thread at a time.
+ */
+#ifndef FWR_H
+#define FWR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FWR_OK = 0,
+  FWR_E_INVAL = -1,        /* bad argument (NULL pointer, size out of range, ...) */
+  FWR_E_UNSUPPORTED = -2,  /* valid request this build does not implement (e.g. grid size) */
+  FWR_E_NOMEM = -3,        /* device allocation failed */
+  FWR_E_DEVICE = -4,       /* HIP runtime error (launch failure, fault, no device) */
+  FWR_E_STATE = -5         /* plan handle not valid */
+} fwr_status;
+
+typedef enum {
+  FWR_MODEL_FRIED = 0      /* Fried-geometry Shack-Hartmann slopes */
+} fwr_model;
+
+typedef struct fwr_plan_s *fwr_plan_t;   /* opaque; owns every device table */
+
+typedef struct {
+  int32_t n_sub;            /* n: lenslets per side, >= 1 */
+  int32_t n_grid;           /* N: padded grid side; N > n, N - n even */
+  const uint8_t *mask;      /* HOST pointer, n*n bytes, row = y; nonzero = valid
+                               subaperture (the pupil P of Algorithm 1 step 4).
+                               Copied at plan time. */
+  int32_t n_iter;           /* Gerchberg iterations, 0 <= n_iter <= 10000 */
+  int32_t periodic;         /* 1: apply Eq. 5 once after the loop (Algorithm 1 step 5) */
+  int32_t periodic_each_iter; /* 1: apply Eq. 5 after every iteration's step 4 as well */
+  int32_t model;            /* fwr_model */
+  double gamma;             /* Eq. 3 gamma for the FINAL reconstruction (the loop always
+                               uses gamma = 0, Sec. 3.3): 0 = LSQ, 1 = MMSE */
+  double noise_var;         /* sigma^2 of the slope noise [rad^2] (W_eta, white) */
+  double r0, L0;            /* von Karman W_phi: Fried parameter and outer scale [m] */
+  double d;                 /* lenslet pitch [m] (grid spacing of the phase) */
+  const double *alpha_map;  /* optional HOST N*N map (row = frequency l along y, column =
+                               frequency k along x, unshifted DFT order) that replaces
+                               gamma * W_eta / W_phi; NULL = use gamma, noise_var, r0, L0, d */
+  int32_t max_batch;        /* largest B accepted by the calls, >= 1 */
+  void *stream;             /* hipStream_t for every call; NULL = the null stream */
+} fwr_params;
+
+/* Create a plan: validates the parameters, builds the filter, twiddle and
+ * geometry tables in double precision on the host, rounds them to float and
+ * uploads them.  Grid sizes handled on-chip: N = 4 * t with
+ * t in {2,3,4,5,6,8,10,12,16,20,32} (N = 8 ... 128).  On success *out holds
+ * the plan; on failure *out is set to NULL. */
+fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out);
+
+/* Algorithm 1 (steps 1-4 n_iter times, then step 5 if periodic) for B frames.
+ * d_slopes: float[B][2][n][n]; d_ext: float[B][2][N][N].  Inside the pupil the
+ * output equals the input bit for bit.  B = 0 is a no-op; B > max_batch or a
+ * NULL pointer with B > 0 gives FWR_E_INVAL. */
+fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B);
+
+/* Extension as fwr_extend, then the final reconstruction of Eq. 2 with the
+ * Eq. 3 filter; writes the (n+1) x (n+1) node window of each frame.
+ * d_slopes: float[B][2][n][n]; d_phase: float[B][n+1][n+1].  Same errors as
+ * fwr_extend. */
+fwr_status fwr_reconstruct(fwr_plan_t plan, const float *d_slopes, float *d_phase, int32_t B);
+
+/* Release the plan and its device tables.  Work already enqueued must have
+ * completed (the call synchronises the plan's stream first).  NULL is
+ * FWR_E_STATE. */
+fwr_status fwr_destroy(fwr_plan_t plan);
+
+/* Change the stream later calls enqueue on. */
+fwr_status fwr_set_stream(fwr_plan_t plan, void *stream);
+
+/* Launch shape of the reconstruction kernel, for reporting: threads per
+ * workgroup, frames per workgroup, dynamic LDS bytes per workgroup. */
+fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
+                                int32_t *lds_bytes);
+
+/* Static description of a status code (never NULL). */
+const char *fwr_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWR_H */

@@ -1,0 +1,245 @@
+// C ABI of libfwr: plan construction (double-precision tables, rounded to
+// float once), argument validation and asynchronous launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fwr.h"
+#include "onchip.h"
+
+
+namespace {
+
+constexpr uint32_t kMagic = 0x46575231u;  // "FWR1"
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Von Karman PSD prefactor [24/5 Gamma(6/5)]^(5/6) Gamma(11/6)^2 / (2 pi^(11/3)).
+double vk_constant() {
+  return std::pow(24.0 / 5.0 * std::tgamma(6.0 / 5.0), 5.0 / 6.0) * std::pow(std::tgamma(11.0 / 6.0), 2.0) /
+         (2.0 * std::pow(kPi, 11.0 / 3.0));
+}
+
+}  // namespace
+
+struct fwr_plan_s {
+  uint32_t magic = 0;
+  int device = 0;
+  int n = 0, N = 0, o = 0, n_iter = 0, flags = 0, max_batch = 0;
+  hipStream_t stream = nullptr;
+  void *d_mem = nullptr;
+  const float *h_loop = nullptr;
+  const float *h_final = nullptr;
+  const float2 *tw_lane = nullptr;
+  const uint32_t *codes = nullptr;
+};
+
+namespace {
+
+bool valid(fwr_plan_t p) { return p != nullptr && p->magic == kMagic; }
+
+// Squared Fried transfer function |G_x|^2 + |G_y|^2 = 4 (u^2 + v^2),
+// u = sin(pi k/N) cos(pi l/N), v = sin(pi l/N) cos(pi k/N).
+double fried_g2(int l, int k, int N) {
+  const double sk = std::sin(kPi * k / N), ck = std::cos(kPi * k / N);
+  const double sl = std::sin(kPi * l / N), cl = std::cos(kPi * l / N);
+  const double u = sk * cl, v = sl * ck;
+  return 4.0 * (u * u + v * v);
+}
+
+bool singular(int l, int k, int N) {
+  return (l == 0 && k == 0) || (N % 2 == 0 && l == N / 2 && k == N / 2);
+}
+
+// gamma * W_eta / W_phi at DFT index (l, k): sigma^2 d^2 / Phi_vK(kappa), kappa = (k', l') / (N d)
+double regulariser(const fwr_params &p, int l, int k) {
+  const int N = p.n_grid;
+  if (p.alpha_map) return p.alpha_map[(size_t)l * N + k];
+  if (p.gamma == 0.0) return 0.0;
+  const int ks = k < (N + 1) / 2 ? k : k - N;
+  const int ls = l < (N + 1) / 2 ? l : l - N;
+  const double kap2 = (double(ks) * ks + double(ls) * ls) / (double(N) * N * p.d * p.d);
+  const double phi = vk_constant() * std::pow(p.r0, -5.0 / 3.0) * std::pow(kap2 + 1.0 / (p.L0 * p.L0), -11.0 / 6.0);
+  return p.gamma * p.noise_var * p.d * p.d / phi;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fwr_status_string(int32_t s) {
+  switch (s) {
+    case FWR_OK: return "ok";
+    case FWR_E_INVAL: return "invalid argument";
+    case FWR_E_UNSUPPORTED: return "unsupported configuration";
+    case FWR_E_NOMEM: return "device allocation failed";
+    case FWR_E_DEVICE: return "HIP runtime error";
+    case FWR_E_STATE: return "invalid plan handle";
+    default: return "unknown status";
+  }
+}
+
+fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
+  if (out == nullptr) return FWR_E_INVAL;
+  *out = nullptr;
+  if (params == nullptr) return FWR_E_INVAL;
+  const fwr_params &p = *params;
+  const int n = p.n_sub, N = p.n_grid;
+  if (n < 1 || N <= n || (N - n) % 2 != 0 || p.mask == nullptr) return FWR_E_INVAL;
+  if (p.n_iter < 0 || p.n_iter > 10000 || p.max_batch < 1) return FWR_E_INVAL;
+  if (p.model != FWR_MODEL_FRIED) return FWR_E_UNSUPPORTED;
+  if (p.alpha_map == nullptr && p.gamma != 0.0) {
+    if (!(p.gamma > 0.0) || !(p.noise_var >= 0.0) || !(p.r0 > 0.0) || !(p.L0 > 0.0) || !(p.d > 0.0))
+      return FWR_E_INVAL;
+  }
+  if (!fwr::onchip_supported(N)) return FWR_E_UNSUPPORTED;
+
+  const int T = N / 4, threads = fwr::onchip_threads(N);
+  static const int beta[4] = {0, 2, 1, 3};
+
+  // host tables
+  std::vector<float> h_loop((size_t)T * threads), h_final((size_t)T * threads);
+  for (int c = 0; c < N; ++c) {
+    const int kf = (c % T) + T * beta[c / T];  // row frequency held in LDS column c
+    for (int jj = 0; jj < 4; ++jj) {
+      const int tt = 4 * c + jj;
+      for (int k2 = 0; k2 < T; ++k2) {
+        const int lf = k2 + T * beta[jj];      // column frequency of this output
+        const double g2 = fried_g2(lf, kf, N);
+        const double norm = 1.0 / (2.0 * double(N) * double(N));
+        double hl = 0.0, hf = 0.0;
+        if (!singular(lf, kf, N)) {
+          hl = norm / g2;
+          const double den = g2 + regulariser(p, lf, kf);
+          hf = den > 0.0 ? norm / den : 0.0;
+        }
+        h_loop[(size_t)tt * T + k2] = float(hl);
+        h_final[(size_t)tt * T + k2] = float(hf);
+      }
+    }
+  }
+  std::vector<float2> tw((size_t)T * 4);
+  for (int k2 = 0; k2 < T; ++k2)
+    for (int jj = 0; jj < 4; ++jj) {
+      const double ang = -2.0 * kPi * double(jj) * double(k2) / double(N);
+      tw[(size_t)k2 * 4 + jj] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
+    }
+  // per-thread node codes: 4 bits per node (m, 4k + j) of thread t = 4m + j; a set bit marks an
+  // adjacent cell outside the pupil: bit 0 (m, n), bit 1 (m-1, n-1), bit 2 (m, n-1), bit 3 (m-1, n)
+  const int o = (N - n) / 2;
+  auto in_pupil = [&](int cm, int cn) {
+    cm = (cm + N) % N;
+    cn = (cn + N) % N;
+    const int i = cm - o, jj = cn - o;
+    return i >= 0 && i < n && jj >= 0 && jj < n && p.mask[(size_t)i * n + jj] != 0;
+  };
+  const int words = (T + 7) / 8;
+  std::vector<uint32_t> codes((size_t)words * threads, 0u);
+  for (int m = 0; m < N; ++m)
+    for (int jj = 0; jj < 4; ++jj)
+      for (int k = 0; k < T; ++k) {
+        const int nn = 4 * k + jj;
+        const uint32_t c = (in_pupil(m, nn) ? 0u : 1u) | (in_pupil(m - 1, nn - 1) ? 0u : 2u) |
+                           (in_pupil(m, nn - 1) ? 0u : 4u) | (in_pupil(m - 1, nn) ? 0u : 8u);
+        codes[(size_t)(k / 8) * threads + 4 * m + jj] |= c << (4 * (k % 8));
+      }
+
+  if (fwr::onchip_lds_bytes(N, n) > 160 * 1024) return FWR_E_UNSUPPORTED;
+  auto *plan = new (std::nothrow) fwr_plan_s();
+  if (plan == nullptr) return FWR_E_NOMEM;
+  if (hipGetDevice(&plan->device) != hipSuccess || fwr::onchip_prepare(N, n) != hipSuccess) {
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t b_h = h_loop.size() * sizeof(float);
+  const size_t b_tw = tw.size() * sizeof(float2);
+  const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
+  const size_t total = off_codes + codes.size() * sizeof(uint32_t);
+  char *mem = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&mem), total) != hipSuccess) {
+    delete plan;
+    return FWR_E_NOMEM;
+  }
+  hipError_t e = hipMemcpy(mem, h_loop.data(), b_h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_hf, h_final.data(), b_h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(mem + off_codes, codes.data(), codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(mem);
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  plan->magic = kMagic;
+  plan->n = n;
+  plan->N = N;
+  plan->o = o;
+  plan->n_iter = p.n_iter;
+  plan->flags = (p.periodic ? fwr::kFlagPeriodic : 0) | (p.periodic_each_iter ? fwr::kFlagPeriodicEach : 0);
+  plan->max_batch = p.max_batch;
+  plan->stream = static_cast<hipStream_t>(p.stream);
+  plan->d_mem = mem;
+  plan->h_loop = reinterpret_cast<const float *>(mem);
+  plan->h_final = reinterpret_cast<const float *>(mem + off_hf);
+  plan->tw_lane = reinterpret_cast<const float2 *>(mem + off_tw);
+  plan->codes = reinterpret_cast<const uint32_t *>(mem + off_codes);
+  *out = plan;
+  return FWR_OK;
+}
+
+static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
+  if (B == 0) return FWR_OK;
+  if (in == nullptr || out == nullptr) return FWR_E_INVAL;
+  fwr::OnchipArgs a;
+  a.slopes = in;
+  a.out = out;
+  a.h_loop = plan->h_loop;
+  a.h_final = plan->h_final;
+  a.tw_lane = plan->tw_lane;
+  a.codes = plan->codes;
+  a.B = B;
+  a.n = plan->n;
+  a.o = plan->o;
+  a.n_iter = plan->n_iter;
+  a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
+  return fwr::onchip_launch(plan->N, a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+}
+
+fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
+  return run(plan, d_slopes, d_ext, B, true);
+}
+
+fwr_status fwr_reconstruct(fwr_plan_t plan, const float *d_slopes, float *d_phase, int32_t B) {
+  return run(plan, d_slopes, d_phase, B, false);
+}
+
+fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
+  if (!valid(plan)) return FWR_E_STATE;
+  plan->stream = static_cast<hipStream_t>(stream);
+  return FWR_OK;
+}
+
+fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
+                                int32_t *lds_bytes) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (threads) *threads = fwr::onchip_threads(plan->N);
+  if (frames_per_group) *frames_per_group = 2;
+  if (lds_bytes) *lds_bytes = fwr::onchip_lds_bytes(plan->N, plan->n);
+  return FWR_OK;
+}
+
+fwr_status fwr_destroy(fwr_plan_t plan) {
+  if (!valid(plan)) return FWR_E_STATE;
+  hipStreamSynchronize(plan->stream);
+  hipFree(plan->d_mem);
+  plan->magic = 0;
+  delete plan;
+  return FWR_OK;
+}
+
+}  // extern "C"

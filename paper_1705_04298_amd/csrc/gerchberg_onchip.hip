@@ -1,0 +1,443 @@
+// On-chip Gerchberg extension + Fourier reconstruction for padded grids N <= 128.
+//
+// One workgroup takes TWO frames.  Everything the loop iterates on is real,
+// and every Fourier-domain operator in it is real and even, so the two frames
+// ride in one complex field (frame A = real part, frame B = imaginary part)
+// and share every FFT.  Per frame pair the loop state lives in registers and
+// one N x N complex LDS tile; HBM is touched only to read the slopes and to
+// write the result.
+//
+// Formulation (Fried model; exact rewrite of Algorithm 1 steps 1-4):
+//   Step 2 of each iteration, phi~ = (G_x* S_x + G_y* S_y) / |G|^2 followed
+//   by s~ = G phi~, is evaluated as
+//     q   = G_x^T s_x + G_y^T s_y          (adjoint Fried stencil, real space)
+//     phi = TF^-1 [ TF(q) / |G|^2 ]        (one real, even Fourier filter)
+//     s'  = G phi                          (Fried stencil, real space)
+//   and step 4 re-imposes the measurement inside the pupil.  With the cell
+//   differences p = s_x + s_y (main diagonal) and r = s_x - s_y (anti-
+//   diagonal), q (times 2) at a node is
+//     q2 = F0 + sum over its 4 surrounding cells c outside the pupil of (phi - phi_c)
+//   where phi_c is the diagonally opposite corner of cell c and F0 collects the
+//   measured p, r of the in-pupil cells (constant over the iterations).
+//   The final reconstruction (Eq. 2 with the Eq. 3 filter) is the same
+//   Fourier step with 1 / (|G|^2 + gamma W_eta/W_phi).
+//
+// Thread layout: 4 lanes per grid line (see fft_lane.h), 4N threads.
+//   row phase    : thread (line = m, lane j) holds nodes (m, 4k + j), k < T
+//   column phase : thread (line = c, lane j) holds rows 4k + j of LDS column c
+// LDS tile: N rows x PITCH complex.  In the row phase a thread's k-th value
+// sits at column T j + k of its row ("lane-blocked"), which makes the row
+// reads of the inverse transform and the writes of the stencil hit the
+// thread's own slots, so they need no barrier in between.
+#include "fft_lane.h"
+#include "onchip.h"
+
+#include <cstdint>
+
+namespace fwr {
+
+template <int N>
+struct Onchip {
+  static constexpr int T = N / 4;
+  static constexpr int THREADS = 4 * N;
+  static constexpr int PITCH = N + 1;     // complex elements per LDS row
+  static constexpr int TILE = N * PITCH;  // complex elements
+  // N <= 80: the per-node forcing F0 of the n+1 window rows lives in LDS (dynamic,
+  // (n+1) * N complex) so that two workgroups share a CU; N = 128 keeps it in
+  // registers (one workgroup per CU).
+  static constexpr bool F0_IN_LDS = N <= 80;
+  static constexpr int STATIC_LDS_BYTES = (TILE + 2 * N + T * 4) * 8;
+  static int lds_bytes(int n) { return STATIC_LDS_BYTES + (F0_IN_LDS ? (n + 1) * N * 8 : 0); }
+};
+
+// c ? a : b on the bit patterns: exact, and both operands are always computed, so
+// the compiler cannot sink the loads feeding one side into a branch
+__device__ __forceinline__ float select_bits(bool c, float a, float b) {
+  const uint32_t m = 0u - static_cast<uint32_t>(c);
+  return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+
+template <int N, bool EACH>
+__global__ __launch_bounds__(Onchip<N>::THREADS) void gerchberg_onchip_kernel(OnchipArgs a) {
+  using C = Onchip<N>;
+  constexpr int T = C::T;
+  constexpr int P = C::PITCH;
+  __shared__ float2 buf[C::TILE];
+  __shared__ float2 sums[2 * N];  // Eq. 5: column sums C_n, then row sums R_m
+  __shared__ float2 tw[T * 4];
+  extern __shared__ float2 f0rows[];  // [(n+1)][N], lane-blocked like the tile rows
+
+  const int t = threadIdx.x;
+  const int line = t >> 2;
+  const int j = t & 3;
+  const QuadLane q(j);
+  const int fa = 2 * blockIdx.x;
+  const bool hasB = fa + 1 < a.B;
+  const int n = a.n, o = a.o;
+  const int up = line == 0 ? N - 1 : line - 1;    // row m - 1
+  const int dn = line == N - 1 ? 0 : line + 1;    // row m + 1
+
+  for (int i = t; i < T * 4; i += C::THREADS) tw[i] = a.tw_lane[i];
+
+  // ---- per-node constants: out-of-pupil cell bits and the in-pupil forcing F0
+  const int plane = n * n;
+  const float *sa = a.slopes + (size_t)fa * 2 * plane;
+  const float *sb = hasB ? sa + 2 * plane : nullptr;
+  const float *sbb = hasB ? sb : sa;  // always-valid pointer for branch-free reads
+  const float bflag = hasB ? 1.f : 0.f;
+  const unsigned uplane = unsigned(plane);
+  uint32_t codes[(T + 7) / 8];
+#pragma unroll
+  for (int w = 0; w < (T + 7) / 8; ++w) codes[w] = a.codes[w * C::THREADS + t];
+  auto code_of = [&](int k) -> uint32_t { return (codes[k >> 3] >> (4 * (k & 7))) & 15u; };
+
+  // F0 = -p(c1) + p(c2) + r(c3) - r(c4) over the in-pupil cells c1 = (m, n), c2 = (m-1, n-1),
+  // c3 = (m, n-1), c4 = (m-1, n), with p = s_x + s_y, r = s_x - s_y.  The window's x slopes,
+  // then its y slopes, are staged in the LDS tile (invalid cells read as zero).
+  float2 f0[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) f0[k] = make_float2(0.f, 0.f);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = t; i < plane; i += C::THREADS) {
+      const float va = sa[pass * plane + i];
+      const float vb = sb ? sb[pass * plane + i] : 0.f;
+      buf[i] = make_float2(va, vb);
+    }
+    __syncthreads();
+    const float sgn3 = pass == 0 ? 1.f : -1.f;  // r = s_x - s_y
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const uint32_t c = code_of(k);
+      const int nn = 4 * k + j;
+      const int nl = nn == 0 ? N - 1 : nn - 1;
+      float2 f = f0[k];
+      if (!(c & 1u)) { const float2 v = buf[(line - o) * n + (nn - o)]; f = csub(f, v); }
+      if (!(c & 2u)) { const float2 v = buf[(up - o) * n + (nl - o)]; f = cadd(f, v); }
+      if (!(c & 4u)) { const float2 v = buf[(line - o) * n + (nl - o)]; f.x = fmaf(sgn3, v.x, f.x); f.y = fmaf(sgn3, v.y, f.y); }
+      if (!(c & 8u)) { const float2 v = buf[(up - o) * n + (nn - o)]; f.x = fmaf(-sgn3, v.x, f.x); f.y = fmaf(-sgn3, v.y, f.y); }
+      f0[k] = f;
+    }
+    __syncthreads();
+  }
+  const bool in_rows = line >= o && line <= o + n;  // rows that can carry forcing
+  if constexpr (C::F0_IN_LDS) {
+    if (in_rows) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) f0rows[(line - o) * N + T * j + k] = f0[k];
+    }
+  }
+  const int f0row = (in_rows ? line - o : 0) * N + T * j;
+  const float rowf = in_rows ? 1.f : 0.f;
+
+  // neighbour column slots for n + 1 and n - 1 (lane-blocked layout)
+  const int jp = (j + 1) & 3, jm = (j + 3) & 3;
+  const int carry = j == 3 ? 1 : 0, borrow = j == 0 ? 1 : 0;
+
+  // ---- Fourier step: x holds q2 (row layout) on entry, phi on exit
+  auto solve = [&](float2 *x, const float *h) {
+    line_fft_fwd<T>(x, tw, j, q);
+#pragma unroll
+    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
+    __syncthreads();
+    float2 y[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) y[k] = buf[(4 * k + j) * P + line];
+    line_fft_fwd<T>(y, tw, j, q);
+    const float *ht = h + t * T;  // thread-contiguous: one address, immediate offsets
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const float hv = ht[k];
+      y[k].x *= hv;
+      y[k].y *= hv;
+    }
+    line_fft_inv<T>(y, tw, j, q);
+#pragma unroll
+    for (int k = 0; k < T; ++k) buf[(4 * k + j) * P + line] = y[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < T; ++k) x[k] = buf[line * P + T * j + k];
+    line_fft_inv<T>(x, tw, j, q);
+  };
+
+  // Only k = T-1 (for n + 1) and k = 0 (for n - 1) can wrap; keeping the wrap
+  // test out of the other (unrolled) indices leaves base + k addresses whose
+  // offsets fold into the LDS instruction.
+  const int base_p = T * jp + carry, base_m = T * jm - borrow;
+  const int wrap_p = j == 3 ? 0 : T * jp + T - 1 + carry;  // slot for k = T-1
+  const int wrap_m = j == 0 ? T * 3 + T - 1 : T * jm;     // slot for k = 0
+  auto slot_p = [&](int k) { return k == T - 1 ? wrap_p : base_p + k; };
+  auto slot_m = [&](int k) { return k == 0 ? wrap_m : base_m + k; };
+
+  // ---- fast stencil: phi (x) -> q2 (x), measured slopes inside the pupil via F0
+  auto stencil = [&](float2 *x) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
+    // keep the per-node weights from being hoisted out of the iteration loop
+    // as 4T live float registers: they are re-derived from 3 code words here
+#pragma unroll
+    for (int w = 0; w < (T + 7) / 8; ++w) asm volatile("" : "+v"(codes[w]));
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int sp = slot_p(k), sm = slot_m(k);
+      const float2 d1 = buf[dn * P + sp];  // (m+1, n+1)
+      const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
+      const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
+      const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
+      const uint32_t c = code_of(k);
+      const float w1 = float(c & 1u), w2 = float((c >> 1) & 1u);
+      const float w3 = float((c >> 2) & 1u), w4 = float((c >> 3) & 1u);
+      const float2 ph = x[k];
+      float2 r;
+      if constexpr (C::F0_IN_LDS) {
+        const float2 fv = f0rows[f0row + k];  // clamped address: always a valid read
+        r = make_float2(fv.x * rowf, fv.y * rowf);
+      } else {
+        r = f0[k];
+      }
+      r.x = fmaf(w1, ph.x - d1.x, r.x);
+      r.y = fmaf(w1, ph.y - d1.y, r.y);
+      r.x = fmaf(w2, ph.x - d2.x, r.x);
+      r.y = fmaf(w2, ph.y - d2.y, r.y);
+      r.x = fmaf(w3, ph.x - d3.x, r.x);
+      r.y = fmaf(w3, ph.y - d3.y, r.y);
+      r.x = fmaf(w4, ph.x - d4.x, r.x);
+      r.y = fmaf(w4, ph.y - d4.y, r.y);
+      x[k] = r;
+      // bound the neighbour reads in flight (4 per node)
+      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+  };
+
+  // ---- final step: phi (x) -> q2 (x) with the measured slopes inside the pupil and,
+  // with `fix`, Eq. 5 applied to the slopes first; with `write` the (optionally
+  // periodised) slopes themselves are written out instead (returns true).
+  //
+  // Eq. 5 only rewrites s_x on column N-1 and s_y on row N-1: with
+  // R_m = sum_n s_x(m, n) and C_n = sum_m s_y(m, n) (all cells, as measured /
+  // extrapolated), s_x(m, N-1) drops by R_m and s_y(N-1, n) by C_n.  Through the
+  // adjoint stencil this moves q2 only on the border node lines:
+  //   node (m, 0)   by -(R_m + R_{m-1}),   node (m, N-1) by +(R_m + R_{m-1}),
+  //   node (0, n)   by -(C_n + C_{n-1}),   node (N-1, n) by +(C_n + C_{n-1}).
+  auto final_step = [&](float2 *x, bool fix, bool write) -> bool {
+#pragma unroll
+    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
+    __syncthreads();
+    const unsigned wrow = unsigned(line >= o && line < o + n ? line - o : 0) * unsigned(n);
+    const size_t gplane = (size_t)N * N;
+    float *ea = a.out + (size_t)fa * 2 * gplane;  // extended slopes of frame A (write mode)
+    float2 rowacc = make_float2(0.f, 0.f), sx_last = make_float2(0.f, 0.f);
+    float2 DY[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int nn = 4 * k + j;
+      const uint32_t c4 = code_of(k);
+      const bool meas = !(c4 & 1u);
+      const unsigned widx = wrow + unsigned(nn >= o && nn < o + n ? nn - o : 0);
+      const float mxa = sa[widx], mya = sa[uplane + widx];
+      const float mxb = sbb[widx] * bflag, myb = sbb[uplane + widx] * bflag;
+      const int sp = slot_p(k), sm = slot_m(k);
+      const float2 ph = x[k];
+      const float2 b = buf[line * P + sp];  // (m, n+1)
+      const float2 c = buf[dn * P + T * j + k];  // (m+1, n)
+      const float2 d1 = buf[dn * P + sp];  // (m+1, n+1)
+      const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
+      const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
+      const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
+      // cell (m, n): s_x = (b - a + d - c) / 2, s_y = (c - a + d - b) / 2
+      const float2 gx = make_float2(0.5f * ((b.x - ph.x) + (d1.x - c.x)), 0.5f * ((b.y - ph.y) + (d1.y - c.y)));
+      const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
+      const float2 sxk = make_float2(select_bits(meas, mxa, gx.x), select_bits(meas, mxb, gx.y));
+      const float2 syk = make_float2(select_bits(meas, mya, gy.x), select_bits(meas, myb, gy.y));
+      rowacc = cadd(rowacc, sxk);
+      DY[k] = syk;
+      if (k == T - 1) sx_last = sxk;
+      if (write) {
+        const size_t idx = (size_t)line * N + nn;
+        ea[idx] = sxk.x;
+        ea[gplane + idx] = syk.x;
+        if (hasB) {
+          ea[2 * gplane + idx] = sxk.y;
+          ea[3 * gplane + idx] = syk.y;
+        }
+      } else {
+        float2 r;
+        if constexpr (C::F0_IN_LDS) {
+          const float2 fv = f0rows[f0row + k];
+          r = make_float2(fv.x * rowf, fv.y * rowf);
+        } else {
+          r = f0[k];
+        }
+        const float w1 = float(c4 & 1u), w2 = float((c4 >> 1) & 1u);
+        const float w3 = float((c4 >> 2) & 1u), w4 = float((c4 >> 3) & 1u);
+        r.x = fmaf(w1, ph.x - d1.x, r.x);
+        r.y = fmaf(w1, ph.y - d1.y, r.y);
+        r.x = fmaf(w2, ph.x - d2.x, r.x);
+        r.y = fmaf(w2, ph.y - d2.y, r.y);
+        r.x = fmaf(w3, ph.x - d3.x, r.x);
+        r.y = fmaf(w3, ph.y - d3.y, r.y);
+        r.x = fmaf(w4, ph.x - d4.x, r.x);
+        r.y = fmaf(w4, ph.y - d4.y, r.y);
+        x[k] = r;
+      }
+      if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (fix) {
+      // R_m: quad reduction of the per-lane partial row sums
+      rowacc.x += dpp_xor1(rowacc.x);
+      rowacc.y += dpp_xor1(rowacc.y);
+      rowacc.x += dpp_xor2(rowacc.x);
+      rowacc.y += dpp_xor2(rowacc.y);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = DY[k];
+      if (j == 0) sums[N + line] = rowacc;
+      __syncthreads();
+      if (t < N) {  // C_n in a fixed order (deterministic)
+        float2 cs = make_float2(0.f, 0.f);
+        const int slot = T * (t & 3) + (t >> 2);
+        for (int m = 0; m < N; ++m) cs = cadd(cs, buf[m * P + slot]);
+        sums[t] = cs;
+      }
+      __syncthreads();
+      const float2 Rm = sums[N + line], Rm1 = sums[N + up];
+      if (write) {
+        if (j == 3) {  // s_x(m, N-1) -= R_m
+          const size_t idx = (size_t)line * N + (N - 1);
+          ea[idx] = sx_last.x - Rm.x;
+          if (hasB) ea[2 * gplane + idx] = sx_last.y - Rm.y;
+        }
+        if (line == N - 1) {  // s_y(N-1, n) -= C_n
+#pragma unroll
+          for (int k = 0; k < T; ++k) {
+            const size_t idx = (size_t)line * N + 4 * k + j;
+            const float2 cn = sums[4 * k + j];
+            ea[gplane + idx] = DY[k].x - cn.x;
+            if (hasB) ea[3 * gplane + idx] = DY[k].y - cn.y;
+          }
+        }
+      } else {
+        const float2 rr = cadd(Rm, Rm1);
+        if (j == 0) x[0] = csub(x[0], rr);          // node (m, 0)
+        if (j == 3) x[T - 1] = cadd(x[T - 1], rr);  // node (m, N-1)
+        if (line == 0 || line == N - 1) {
+#pragma unroll
+          for (int k = 0; k < T; ++k) {
+            const int nn = 4 * k + j;
+            const float2 cc = cadd(sums[nn], sums[nn == 0 ? N - 1 : nn - 1]);
+            x[k] = line == 0 ? csub(x[k], cc) : cadd(x[k], cc);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    return write;
+  };
+
+  const bool periodic = (a.flags & kFlagPeriodic) != 0;
+  const bool extend = (a.flags & kFlagExtend) != 0;
+  const bool need_final_step = periodic || extend || (EACH && a.n_iter > 0);
+  const bool fix_final = periodic || (EACH && a.n_iter > 0);
+
+  float2 x[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) x[k] = f0[k];  // q2 of the zero-padded start
+  __syncthreads();                           // tables and forcing in LDS
+
+  for (int it = 0; it < a.n_iter; ++it) {
+    solve(x, a.h_loop);
+    if (it == a.n_iter - 1) break;
+    if constexpr (EACH) final_step(x, true, false);
+    else stencil(x);
+  }
+  if (need_final_step) {
+    if (a.n_iter == 0) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) x[k] = make_float2(0.f, 0.f);  // phi = 0
+    }
+    if (final_step(x, fix_final, extend)) return;
+  } else if (a.n_iter > 0) {
+    stencil(x);
+  }
+  solve(x, a.h_final);
+
+  // (n+1) x (n+1) node window
+  if (line >= o && line <= o + n) {
+    float *oa = a.out + (size_t)fa * (n + 1) * (n + 1);
+    float *ob = oa + (size_t)(n + 1) * (n + 1);
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int nn = 4 * k + j;
+      if (nn >= o && nn <= o + n) {
+        const size_t idx = (size_t)(line - o) * (n + 1) + (nn - o);
+        oa[idx] = x[k].x;
+        if (hasB) ob[idx] = x[k].y;
+      }
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s) {
+  const int groups = (a.B + 1) / 2;
+  const size_t dyn = Onchip<N>::F0_IN_LDS ? size_t(a.n + 1) * N * 8 : 0;
+  if (a.flags & kFlagPeriodicEach)
+    hipLaunchKernelGGL((gerchberg_onchip_kernel<N, true>), dim3(groups), dim3(Onchip<N>::THREADS), dyn, s, a);
+  else
+    hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false>), dim3(groups), dim3(Onchip<N>::THREADS), dyn, s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t prepare_onchip(int n) {
+  // dynamic LDS above the default 64 KiB window must be requested explicitly
+  const int dyn = Onchip<N>::F0_IN_LDS ? (n + 1) * N * 8 : 0;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  return e;
+}
+
+#define FWR_ONCHIP_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(128)
+
+bool onchip_supported(int N) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return true;
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return false;
+  }
+}
+
+int onchip_threads(int N) { return 4 * N; }
+int onchip_lds_bytes(int N, int n) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return Onchip<NN>::lds_bytes(n);
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return 0;
+  }
+}
+
+hipError_t onchip_prepare(int N, int n) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return prepare_onchip<NN>(n);
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return launch_onchip<NN>(a, s);
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fwr

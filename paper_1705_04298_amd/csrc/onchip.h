@@ -1,0 +1,30 @@
+// Launch interface of the on-chip (LDS-resident) Gerchberg kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fwr {
+
+enum : int { kFlagPeriodic = 1, kFlagPeriodicEach = 2, kFlagExtend = 4 };
+
+struct OnchipArgs {
+  const float *slopes;    // [B][2][n][n]
+  float *out;             // [B][n+1][n+1], or [B][2][N][N] with kFlagExtend
+  const float *h_loop;    // [4N][T]: loop filter for thread t's k-th column-phase output
+  const float *h_final;   // [4N][T]: final (Wiener) filter, same layout
+  const float2 *tw_lane;  // [T][4]: W_N^(j k)
+  const uint32_t *codes;  // [(T+7)/8][4N]: 4 bits per node of thread t, nodes 8w..8w+7 in word w;
+                          // bit 0: cell (m, n) outside the pupil, bit 1: cell (m-1, n-1),
+                          // bit 2: cell (m, n-1), bit 3: cell (m-1, n)
+  int B, n, o, n_iter, flags;
+};
+
+bool onchip_supported(int N);
+int onchip_threads(int N);
+int onchip_lds_bytes(int N, int n);   // per workgroup, static + dynamic
+hipError_t onchip_prepare(int N, int n); // once per plan, before the first launch
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s);
+
+}  // namespace fwr

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libfwr (C ABI in include/fwr.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  torch is used for device memory and streams.  If the library is
+missing or fails to load this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwr.so")
+
+FWR_OK = 0
+FWR_E_INVAL = -1
+FWR_E_UNSUPPORTED = -2
+FWR_E_NOMEM = -3
+FWR_E_DEVICE = -4
+FWR_E_STATE = -5
+FWR_MODEL_FRIED = 0
+
+# grid sizes handled by the on-chip kernel (N = 4 t)
+ONCHIP_GRIDS = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 128)
+
+EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set_stream",
+            "fwr_plan_launch_info", "fwr_status_string")
+
+
+class FwrParams(ctypes.Structure):
+    _fields_ = [
+        ("n_sub", ctypes.c_int32),
+        ("n_grid", ctypes.c_int32),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("n_iter", ctypes.c_int32),
+        ("periodic", ctypes.c_int32),
+        ("periodic_each_iter", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("noise_var", ctypes.c_double),
+        ("r0", ctypes.c_double),
+        ("L0", ctypes.c_double),
+        ("d", ctypes.c_double),
+        ("alpha_map", ctypes.POINTER(ctypes.c_double)),
+        ("max_batch", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class FwrError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Open libfwr.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} not found: build it with `python -m paper_1705_04298_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.fwr_plan.argtypes = [ctypes.POINTER(FwrParams), ctypes.POINTER(ctypes.c_void_p)]
+    lib.fwr_plan.restype = ctypes.c_int
+    for name in ("fwr_extend", "fwr_reconstruct"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        f.restype = ctypes.c_int
+    lib.fwr_destroy.argtypes = [ctypes.c_void_p]
+    lib.fwr_destroy.restype = ctypes.c_int
+    lib.fwr_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.fwr_set_stream.restype = ctypes.c_int
+    lib.fwr_plan_launch_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.fwr_plan_launch_info.restype = ctypes.c_int
+    lib.fwr_status_string.argtypes = [ctypes.c_int32]
+    lib.fwr_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().fwr_status_string(int(status)).decode()
+
+
+# ----------------------------------------------------------------- raw C calls
+
+def fwr_plan(params: FwrParams) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = load().fwr_plan(ctypes.byref(params), ctypes.byref(h))
+    if st != FWR_OK:
+        raise FwrError(st, "fwr_plan")
+    return h
+
+
+def fwr_extend(plan, d_slopes: int, d_ext: int, B: int) -> int:
+    return load().fwr_extend(plan, ctypes.c_void_p(d_slopes), ctypes.c_void_p(d_ext), int(B))
+
+
+def fwr_reconstruct(plan, d_slopes: int, d_phase: int, B: int) -> int:
+    return load().fwr_reconstruct(plan, ctypes.c_void_p(d_slopes), ctypes.c_void_p(d_phase), int(B))
+
+
+def fwr_destroy(plan) -> int:
+    return load().fwr_destroy(plan)
+
+
+def fwr_set_stream(plan, stream: int) -> int:
+    return load().fwr_set_stream(plan, ctypes.c_void_p(stream))
+
+
+def fwr_plan_launch_info(plan):
+    t, f, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    st = load().fwr_plan_launch_info(plan, ctypes.byref(t), ctypes.byref(f), ctypes.byref(l))
+    if st != FWR_OK:
+        raise FwrError(st, "fwr_plan_launch_info")
+    return t.value, f.value, l.value
+
+
+# ----------------------------------------------------------------- convenience
+
+def _current_stream() -> int:
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A reconstruction plan bound to the current device and (by default) torch's current stream.
+
+    Inputs and outputs are torch CUDA float32 tensors, C-contiguous:
+    slopes ``[B, 2, n, n]``; phase ``[B, n+1, n+1]``; extended slopes ``[B, 2, N, N]``.
+    """
+
+    def __init__(self, n_sub: int, n_grid: int, mask, n_iter: int = 10, periodic: bool = True,
+                 periodic_each_iter: bool = False, gamma: float = 1.0, noise_var: float = 0.05 ** 2,
+                 r0: float = 0.15, L0: float = 25.0, d: float = 0.2,
+                 alpha_map: Optional[np.ndarray] = None, max_batch: int = 4096,
+                 stream: Optional[int] = None):
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if mask.shape != (n_sub, n_sub):
+            raise ValueError(f"mask must be {n_sub}x{n_sub}")
+        self._mask = mask
+        self._alpha = None if alpha_map is None else np.ascontiguousarray(alpha_map, dtype=np.float64)
+        self.n_sub, self.n_grid, self.max_batch = int(n_sub), int(n_grid), int(max_batch)
+        self.stream = _current_stream() if stream is None else int(stream)
+        p = FwrParams()
+        p.n_sub, p.n_grid = self.n_sub, self.n_grid
+        p.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.n_iter, p.periodic, p.periodic_each_iter = int(n_iter), int(bool(periodic)), int(bool(periodic_each_iter))
+        p.model = FWR_MODEL_FRIED
+        p.gamma, p.noise_var, p.r0, p.L0, p.d = float(gamma), float(noise_var), float(r0), float(L0), float(d)
+        p.alpha_map = (self._alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                       if self._alpha is not None else None)
+        p.max_batch = self.max_batch
+        p.stream = self.stream
+        self._h = fwr_plan(p)
+
+    def _check(self, t, shape, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def reconstruct(self, slopes, out=None):
+        import torch
+        B = slopes.shape[0]
+        self._check(slopes, (B, 2, self.n_sub, self.n_sub), "slopes")
+        if out is None:
+            out = torch.empty((B, self.n_sub + 1, self.n_sub + 1), device=slopes.device, dtype=torch.float32)
+        self._check(out, (B, self.n_sub + 1, self.n_sub + 1), "out")
+        st = fwr_reconstruct(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_reconstruct")
+        return out
+
+    def extend(self, slopes, out=None):
+        import torch
+        B = slopes.shape[0]
+        self._check(slopes, (B, 2, self.n_sub, self.n_sub), "slopes")
+        if out is None:
+            out = torch.empty((B, 2, self.n_grid, self.n_grid), device=slopes.device, dtype=torch.float32)
+        self._check(out, (B, 2, self.n_grid, self.n_grid), "out")
+        st = fwr_extend(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_extend")
+        return out
+
+    def launch_info(self):
+        return fwr_plan_launch_info(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            fwr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,203 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances: the reconstructed phase must match the oracle to a relative rms
+error <= 1e-5 per frame (float32 path vs float64 oracle); extended slopes to
+1e-5 of the frame's rms slope; measured in-pupil slopes bit for bit.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fwr_oracle as O
+from paper_1705_04298_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+REL_TOL = 1e-5
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fwr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_04298_amd import fwr as F
+    F.load()
+    return F
+
+
+def rel_rms(got, want):
+    den = np.sqrt(np.mean(want ** 2))
+    return np.sqrt(np.mean((got - want) ** 2)) / max(den, 1e-300)
+
+
+def run_case(F, slopes, mask, p: O.Params, what="reconstruct"):
+    n, N = p.n_sub, p.n_grid
+    plan = F.Plan(n, N, mask, n_iter=p.n_iter, periodic=p.periodic,
+                  periodic_each_iter=p.periodic_each_iter, gamma=p.gamma, noise_var=p.noise_var,
+                  r0=p.r0, L0=p.L0, d=p.d, max_batch=max(1, slopes.shape[0]))
+    x = torch.from_numpy(np.ascontiguousarray(slopes, dtype=np.float32)).cuda()
+    if what == "reconstruct":
+        out = plan.reconstruct(x)
+    else:
+        out = plan.extend(x)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    plan.close()
+    return res
+
+
+def check_reconstruct(F, slopes, mask, p, tag):
+    _flush(f"[gpu] reconstruct {tag} n={p.n_sub} N={p.n_grid} B={slopes.shape[0]} it={p.n_iter} "
+           f"per={p.periodic} each={p.periodic_each_iter} gamma={p.gamma}")
+    got = run_case(F, slopes, mask, p)
+    s32 = slopes.astype(np.float32).astype(np.float64)  # the oracle sees the same float32 inputs
+    for b in range(slopes.shape[0]):
+        want = O.reconstruct(s32[b], mask, p)
+        if np.all(want == 0):
+            assert np.abs(got[b]).max() < 1e-6
+            continue
+        e = rel_rms(got[b], want)
+        assert e <= REL_TOL, (tag, b, e)
+
+
+SPHERE = dict(n_sub=40, n_grid=80, d=0.2, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
+
+
+def test_sphere40_periodic_10_iterations(fwr):
+    """The 40x40 SPHERE-like frame, 10 iterations, Eq. 5 after the loop, MMSE final filter."""
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 5, dtype=np.float64)   # odd batch: the last pair is half empty
+    check_reconstruct(fwr, slopes, mask, O.Params(n_iter=10, periodic=True, **SPHERE), "sphere")
+
+
+@pytest.mark.parametrize("n_iter,periodic,each", [(0, False, False), (0, True, False), (1, False, False),
+                                                  (2, True, False), (3, False, False), (4, True, True)])
+def test_sphere40_variants(fwr, n_iter, periodic, each):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 2, start=20, dtype=np.float64)
+    check_reconstruct(fwr, slopes, mask,
+                      O.Params(n_iter=n_iter, periodic=periodic, periodic_each_iter=each, **SPHERE),
+                      "variant")
+
+
+def test_lsq_final_filter(fwr):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 2, start=30, dtype=np.float64)
+    check_reconstruct(fwr, slopes, mask, O.Params(n_iter=5, periodic=True, gamma=0.0, **SPHERE), "lsq")
+
+
+@pytest.mark.parametrize("N,n", [(8, 4), (8, 6), (12, 6), (16, 8), (16, 2), (20, 10), (24, 12),
+                                 (32, 16), (40, 20), (48, 24), (64, 32), (80, 78), (128, 64)])
+def test_grid_sizes(fwr, N, n):
+    """Every on-chip grid size, random masks, white slopes; includes n = N - 2 (thin border)."""
+    mask = I.random_mask(n, seed=N * 1000 + n)
+    slopes = I.random_slopes(3, n, seed=N + n)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=6, periodic=True, gamma=1.0, noise_var=0.01, r0=0.15,
+                 L0=25.0, d=8.0 / n)
+    check_reconstruct(fwr, slopes, mask, p, f"grid{N}")
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_extend_matches_oracle_and_keeps_measurement(fwr, periodic):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 3, start=40, dtype=np.float32)
+    p = O.Params(n_iter=7, periodic=periodic, **SPHERE)
+    _flush(f"[gpu] extend periodic={periodic}")
+    got = run_case(fwr, slopes, mask, p, what="extend")
+    s64 = slopes.astype(np.float64)
+    o = 20
+    for b in range(3):
+        ref = O.extend(s64[b], mask, p)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(got[b, 0] - ref.sx).max() <= 10 * REL_TOL * scale
+        assert np.abs(got[b, 1] - ref.sy).max() <= 10 * REL_TOL * scale
+        m = mask.astype(bool)
+        # measured slopes come back bit for bit
+        assert np.array_equal(got[b, 0, o:o + 40, o:o + 40][m].astype(np.float32), slopes[b, 0][m])
+        assert np.array_equal(got[b, 1, o:o + 40, o:o + 40][m].astype(np.float32), slopes[b, 1][m])
+        if periodic:
+            assert np.abs(got[b, 0].sum(axis=1)).max() < 1e-3 * scale * 80
+            assert np.abs(got[b, 1].sum(axis=0)).max() < 1e-3 * scale * 80
+
+
+def test_out_of_pupil_values_are_ignored(fwr):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 2, start=50, dtype=np.float32)
+    g = slopes.copy()
+    g[:, :, mask == 0] = 123.0
+    p = O.Params(n_iter=3, periodic=True, **SPHERE)
+    assert np.array_equal(run_case(fwr, slopes, mask, p), run_case(fwr, g, mask, p))
+
+
+def test_bitwise_deterministic(fwr):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 6, start=60, dtype=np.float32)
+    p = O.Params(n_iter=10, periodic=True, **SPHERE)
+    a = run_case(fwr, slopes, mask, p)
+    b = run_case(fwr, slopes, mask, p)
+    assert np.array_equal(a, b)
+
+
+def test_frames_outside_a_pair_are_isolated(fwr):
+    """Frames are processed two per workgroup; a non-finite frame can only reach its partner."""
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 6, start=70, dtype=np.float32)
+    p = O.Params(n_iter=4, periodic=True, **SPHERE)
+    clean = run_case(fwr, slopes, mask, p)
+    bad = slopes.copy()
+    assert mask[20, 3] == 1       # a valid subaperture (the centre is obstructed)
+    bad[2, 0, 20, 3] = np.nan
+    dirty = run_case(fwr, bad, mask, p)
+    for b in (0, 1, 4, 5):
+        assert np.array_equal(clean[b], dirty[b])
+    assert np.isnan(dirty[2]).any()
+
+
+def test_abi_errors(fwr):
+    F = fwr
+    mask = I.pupil_mask(40)
+    plan = F.Plan(40, 80, mask, max_batch=4)
+    x = torch.zeros((5, 2, 40, 40), device="cuda")
+    y = torch.zeros((5, 41, 41), device="cuda")
+    assert F.fwr_reconstruct(plan._h, x.data_ptr(), y.data_ptr(), 5) == F.FWR_E_INVAL
+    assert F.fwr_reconstruct(plan._h, 0, y.data_ptr(), 2) == F.FWR_E_INVAL
+    assert F.fwr_reconstruct(plan._h, x.data_ptr(), 0, 2) == F.FWR_E_INVAL
+    assert F.fwr_reconstruct(plan._h, 0, 0, 0) == F.FWR_OK          # empty batch is a no-op
+    assert F.fwr_reconstruct(plan._h, x.data_ptr(), y.data_ptr(), -1) == F.FWR_E_INVAL
+    assert F.fwr_extend(None, x.data_ptr(), y.data_ptr(), 1) == F.FWR_E_STATE
+    plan.close()
+    with pytest.raises(F.FwrError):
+        F.Plan(40, 81, mask)          # N - n odd
+    with pytest.raises(F.FwrError):
+        F.Plan(40, 40, mask)          # N <= n
+    with pytest.raises(F.FwrError) as e:
+        F.Plan(40, 84, mask)          # not an on-chip size
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+
+
+def test_full_batch_sampled(fwr):
+    """4096 frames in one launch (the batched workload); 12 frames checked against the oracle."""
+    mask = I.pupil_mask(40)
+    B = 4096
+    rng = np.random.default_rng(5)
+    base = I.make_batch(I.SPHERE_40_BATCH, 64, dtype=np.float32)
+    # tile 64 distinct generated frames with per-frame sign/scale changes (keeps generation fast)
+    slopes = np.empty((B, 2, 40, 40), dtype=np.float32)
+    scales = rng.uniform(0.5, 1.5, B).astype(np.float32)
+    for b in range(B):
+        slopes[b] = base[b % 64] * scales[b]
+    p = O.Params(n_iter=10, periodic=True, **SPHERE)
+    _flush("[gpu] full batch 4096")
+    got = run_case(fwr, slopes, mask, p)
+    for b in rng.choice(B, 12, replace=False):
+        want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
+        assert rel_rms(got[b], want) <= REL_TOL, b
