@@ -53,6 +53,8 @@ def make_inputs(B: int, workers: int) -> np.ndarray:
 
 
 _CPU_SLOPES = None
+KERNEL_SOURCES = ("gerchberg_onchip.hip", "fft_lane.h", "onchip.h")
+PROFILE = os.path.join(ROOT, "profiles", "gerchberg_onchip_80x80_b4096.md")
 
 
 def _oracle_frames(idx):
@@ -60,24 +62,50 @@ def _oracle_frames(idx):
     p = O.Params(n_sub=N_SUB, n_grid=N_GRID, n_iter=N_ITER, periodic=True, gamma=1.0,
                  noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=0.2)
     mask = I.pupil_mask(N_SUB)
-    for i in idx:
-        O.reconstruct(_CPU_SLOPES[i].astype(np.float64), mask, p)
-    return len(idx)
+    return [(i, O.reconstruct(_CPU_SLOPES[i].astype(np.float64), mask, p)) for i in idx]
 
 
-def cpu_baseline(slopes: np.ndarray, workers: int, sample: int) -> dict:
-    """The FP64 oracle, unchanged, over `sample` frames split across `workers` processes."""
+def cpu_baseline(slopes: np.ndarray, workers: int, sample: int):
+    """The FP64 oracle, unchanged, over `sample` frames split across `workers` processes.
+    Returns the timing record and the oracle's phases (for the parity figure)."""
     global _CPU_SLOPES
     _CPU_SLOPES = slopes
     idx = np.arange(sample)
     parts = [idx[w::workers] for w in range(workers)]
     with mp.get_context("fork").Pool(workers) as pool:
         t0 = time.perf_counter()
-        done = sum(pool.map(_oracle_frames, parts))
+        res = pool.map(_oracle_frames, parts)
         dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "frames/s", "cores": workers, "kind": "oracle",
-            "sample": f"first {sample} frames of the benchmark batch, FP64 NumPy oracle, "
-                      f"{workers} single-threaded worker processes, {dt:.1f} s wall"}
+    ref = {i: ph for part in res for i, ph in part}
+    rec = {"value": len(ref) / dt, "unit": "frames/s", "cores": workers, "kind": "oracle",
+           "sample": f"first {sample} frames of the benchmark batch, FP64 NumPy oracle, "
+                     f"{workers} single-threaded worker processes, {dt:.1f} s wall"}
+    return rec, ref
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1705_04298_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed rocprofv3 summary, if it was taken on these sources."""
+    try:
+        with open(PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("source_fingerprint:", "traffic_bytes_per_launch:")))
+    if fields.get("source_fingerprint", "").strip() != kernel_fingerprint():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -87,8 +115,26 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes for input generation (0 = up to 16; use 1 under a profiler)")
+    ap.add_argument("--workload", choices=("sphere40", "elt128"), default="sphere40",
+                    help="sphere40: the headline 4096 x 40x40 batch; elt128: 128 x 128x128 frames on "
+                         "the 256x256 multi-pass path (prints its own line)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration * (1 << 18), device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
+    if args.workload == "elt128":
+        return elt_main(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (frames are independent; see the design notes "
               f"for how the batch shards): --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -96,12 +142,15 @@ def main():
 
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
-    slopes = make_inputs(args.batch, workers)
+    if args.gen_workers == 1:
+        slopes = I.make_batch(I.SPHERE_40_BATCH, args.batch, dtype=np.float32)
+    else:
+        slopes = make_inputs(args.batch, args.gen_workers or workers)
     print(f"[bench] generated {args.batch} frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    cpu = None
+    cpu, ref = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(slopes, workers, min(args.cpu_sample, args.batch))
+        cpu, ref = cpu_baseline(slopes, workers, min(args.cpu_sample, args.batch))
         print(f"[bench] cpu baseline {cpu['value']:.0f} frames/s", file=sys.stderr, flush=True)
 
     import torch
@@ -137,6 +186,12 @@ def main():
 
     flops = algorithmic_flops_per_frame(N_GRID, N_ITER) * args.batch
     achieved = flops / (per_launch_ms / 1e3)
+    parity = None
+    if ref is not None:
+        got = out.cpu().numpy().astype(np.float64)
+        errs = [np.sqrt(np.mean((got[i] - want) ** 2) / np.mean(want ** 2)) for i, want in ref.items()]
+        parity = {"frames": len(errs), "max_rel_rms": float(np.max(errs)),
+                  "median_rel_rms": float(np.median(errs)), "tolerance": 1e-5}
     line = {
         "metric": "frames/s (40x40 SH, 10 Gerchberg iters) + rms phase err vs FP64 oracle",
         "value": frames_per_s,
@@ -155,14 +210,47 @@ def main():
                                "noise 0.05 rad",
                    "batch": args.batch, "n_sub": N_SUB, "n_grid": N_GRID, "n_iter": N_ITER,
                    "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds},
+        "rms_phase_error_vs_oracle": parity,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": profiled_traffic(),
                      "kernel_ms": per_launch_ms,
                      "flops_per_frame": algorithmic_flops_per_frame(N_GRID, N_ITER)},
         "cpu_baseline": cpu,
     }
     plan.close()
     print(json.dumps(line), flush=True)
+
+
+def elt_main(args):
+    """128 frames of 128x128 subapertures (D = 39 m) padded to 256x256, 20 iterations, multi-pass.
+    HBM-bound: roofline against 8 TB/s with 2 MiB per frame-iteration + 128 KiB of slopes."""
+    import torch
+    from paper_1705_04298_amd import fwr
+    B, n, N, n_iter = 128, 128, 256, 20
+    slopes = I.make_batch(I.ELT_128, B, dtype=np.float32)
+    torch.cuda.set_device(0)
+    plan = fwr.Plan(n, N, I.pupil_mask(n), n_iter=n_iter, periodic=True, gamma=1.0,
+                    noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=39.0 / n, max_batch=B)
+    x = torch.from_numpy(slopes).cuda()
+    out = torch.empty((B, n + 1, n + 1), device="cuda", dtype=torch.float32)
+    for _ in range(args.warmup):
+        plan.reconstruct(x, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.reconstruct(x, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    alg_bytes = B * (n_iter * 2 * 2 ** 20 + 2 * 2 ** 16)
+    plan.close()
+    print(json.dumps({"metric": "frames/s (128x128 SH, 256x256 grid, 20 Gerchberg iters)",
+                      "value": B / (ms / 1e3), "unit": "frames/s", "ms_per_step": ms, "steps": args.steps,
+                      "dtype": "f32", "data": "synthetic",
+                      "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": 8000.0,
+                                   "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / 8e12, "traffic": None}}),
+          flush=True)
 
 
 if __name__ == "__main__":

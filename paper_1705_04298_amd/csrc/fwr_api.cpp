@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fwr.h"
+#include "multipass.h"
 #include "onchip.h"
 
 
@@ -35,6 +36,9 @@ struct fwr_plan_s {
   const float *h_final = nullptr;
   const float2 *tw_lane = nullptr;
   const uint32_t *codes = nullptr;
+  // multi-pass path (N = 256)
+  bool multipass = false;
+  fwr::MPArgs mp{};
 };
 
 namespace {
@@ -66,6 +70,20 @@ double regulariser(const fwr_params &p, int l, int k) {
   return p.gamma * p.noise_var * p.d * p.d / phi;
 }
 
+// 1 / (2 |G|^2 N^2) (loop) and 1 / (2 (|G|^2 + gamma W_eta/W_phi) N^2) (final), 0 on the singular set
+void filter_values(const fwr_params &p, int l, int k, double &hl, double &hf) {
+  const int N = p.n_grid;
+  const double norm = 1.0 / (2.0 * double(N) * double(N));
+  hl = hf = 0.0;
+  if (singular(l, k, N)) return;
+  const double g2 = fried_g2(l, k, N);
+  hl = norm / g2;
+  const double den = g2 + regulariser(p, l, k);
+  hf = den > 0.0 ? norm / den : 0.0;
+}
+
+fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out);
+
 }  // namespace
 
 extern "C" {
@@ -95,6 +113,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
     if (!(p.gamma > 0.0) || !(p.noise_var >= 0.0) || !(p.r0 > 0.0) || !(p.L0 > 0.0) || !(p.d > 0.0))
       return FWR_E_INVAL;
   }
+  if (fwr::multipass_supported(N)) return plan_multipass(p, out);
   if (!fwr::onchip_supported(N)) return FWR_E_UNSUPPORTED;
 
   const int T = N / 4, threads = fwr::onchip_threads(N);
@@ -108,14 +127,8 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
       const int tt = 4 * c + jj;
       for (int k2 = 0; k2 < T; ++k2) {
         const int lf = k2 + T * beta[jj];      // column frequency of this output
-        const double g2 = fried_g2(lf, kf, N);
-        const double norm = 1.0 / (2.0 * double(N) * double(N));
-        double hl = 0.0, hf = 0.0;
-        if (!singular(lf, kf, N)) {
-          hl = norm / g2;
-          const double den = g2 + regulariser(p, lf, kf);
-          hf = den > 0.0 ? norm / den : 0.0;
-        }
+        double hl, hf;
+        filter_values(p, lf, kf, hl, hf);
         h_loop[(size_t)tt * T + k2] = float(hl);
         h_final[(size_t)tt * T + k2] = float(hf);
       }
@@ -169,7 +182,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   if (e == hipSuccess)
     e = hipMemcpy(mem + off_codes, codes.data(), codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(mem);
+    (void)hipFree(mem);
     delete plan;
     return FWR_E_DEVICE;
   }
@@ -195,6 +208,13 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (in == nullptr || out == nullptr) return FWR_E_INVAL;
+  if (plan->multipass) {
+    fwr::MPArgs a = plan->mp;
+    a.slopes = in;
+    a.out = out;
+    a.B = B;
+    return fwr::multipass_run(a, extend, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  }
   fwr::OnchipArgs a;
   a.slopes = in;
   a.out = out;
@@ -227,6 +247,12 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes) {
   if (!valid(plan)) return FWR_E_STATE;
+  if (plan->multipass) {
+    if (threads) *threads = 256;
+    if (frames_per_group) *frames_per_group = 2;
+    if (lds_bytes) *lds_bytes = 0;
+    return FWR_OK;
+  }
   if (threads) *threads = fwr::onchip_threads(plan->N);
   if (frames_per_group) *frames_per_group = 2;
   if (lds_bytes) *lds_bytes = fwr::onchip_lds_bytes(plan->N, plan->n);
@@ -235,11 +261,103 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
 
 fwr_status fwr_destroy(fwr_plan_t plan) {
   if (!valid(plan)) return FWR_E_STATE;
-  hipStreamSynchronize(plan->stream);
-  hipFree(plan->d_mem);
+  (void)hipStreamSynchronize(plan->stream);
+  (void)hipFree(plan->d_mem);
   plan->magic = 0;
   delete plan;
   return FWR_OK;
 }
 
 }  // extern "C"
+
+namespace {
+
+fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
+  const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
+  // filter tables: [column position c][row position q], position -> frequency (pos / 16) + 16 (pos % 16)
+  auto freq = [](int pos) { return (pos >> 4) + 16 * (pos & 15); };
+  std::vector<float> hl((size_t)N * N), hf((size_t)N * N);
+  for (int c = 0; c < N; ++c)
+    for (int q = 0; q < N; ++q) {
+      double a, b;
+      filter_values(p, freq(q), freq(c), a, b);
+      hl[(size_t)c * N + q] = float(a);
+      hf[(size_t)c * N + q] = float(b);
+    }
+  std::vector<float2> tw(N);
+  for (int e = 0; e < N; ++e) {
+    const double ang = -2.0 * kPi * double(e) / double(N);
+    tw[e] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
+  }
+  std::vector<uint8_t> mask((size_t)n * n);
+  for (size_t i = 0; i < mask.size(); ++i) mask[i] = p.mask[i] ? 1 : 0;
+  auto in_pupil = [&](int cm, int cn) {
+    cm = (cm + N) % N;
+    cn = (cn + N) % N;
+    const int i = cm - o, jj = cn - o;
+    return i >= 0 && i < n && jj >= 0 && jj < n && mask[(size_t)i * n + jj] != 0;
+  };
+  std::vector<uint8_t> codes((size_t)N * N);
+  for (int m = 0; m < N; ++m)
+    for (int nn = 0; nn < N; ++nn)
+      codes[(size_t)m * N + nn] = uint8_t((in_pupil(m, nn) ? 0 : 1) | (in_pupil(m - 1, nn - 1) ? 0 : 2) |
+                                          (in_pupil(m, nn - 1) ? 0 : 4) | (in_pupil(m - 1, nn) ? 0 : 8));
+
+  auto *plan = new (std::nothrow) fwr_plan_s();
+  if (plan == nullptr) return FWR_E_NOMEM;
+  if (hipGetDevice(&plan->device) != hipSuccess) {
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t b_h = hl.size() * sizeof(float), b_tw = tw.size() * sizeof(float2);
+  const size_t off_hf = b_h, off_tw = 2 * b_h, off_mask = off_tw + b_tw, off_codes = off_mask + mask.size();
+  const size_t off_ws = (off_codes + codes.size() + 255) & ~size_t(255);
+  const size_t ws = fwr::multipass_workspace_bytes(N, n, p.max_batch);
+  char *mem = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&mem), off_ws + ws) != hipSuccess) {
+    delete plan;
+    return FWR_E_NOMEM;
+  }
+  hipError_t e = hipMemcpy(mem, hl.data(), b_h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_hf, hf.data(), b_h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_codes, codes.data(), codes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t pairs = (size_t)(p.max_batch + 1) / 2;
+  const size_t fbytes = (size_t)N * N * sizeof(float2);
+  char *w = mem + off_ws;
+  fwr::MPArgs &a = plan->mp;
+  a.phi = reinterpret_cast<float2 *>(w);
+  a.spec = reinterpret_cast<float2 *>(w + pairs * fbytes);
+  a.sx = reinterpret_cast<float2 *>(w + 2 * pairs * fbytes);
+  a.sy = reinterpret_cast<float2 *>(w + 3 * pairs * fbytes);
+  a.f0 = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes);
+  a.sums = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes + pairs * (size_t)(n + 1) * N * sizeof(float2));
+  a.h_loop = reinterpret_cast<const float *>(mem);
+  a.h_final = reinterpret_cast<const float *>(mem + off_hf);
+  a.tw256 = reinterpret_cast<const float2 *>(mem + off_tw);
+  a.mask = reinterpret_cast<const uint8_t *>(mem + off_mask);
+  a.codes = reinterpret_cast<const uint8_t *>(mem + off_codes);
+  a.n = n;
+  a.o = o;
+  a.n_iter = p.n_iter;
+  a.flags = (p.periodic ? fwr::kMPPeriodic : 0) | (p.periodic_each_iter ? fwr::kMPPeriodicEach : 0);
+  plan->magic = kMagic;
+  plan->n = n;
+  plan->N = N;
+  plan->o = o;
+  plan->n_iter = p.n_iter;
+  plan->max_batch = p.max_batch;
+  plan->stream = static_cast<hipStream_t>(p.stream);
+  plan->d_mem = mem;
+  plan->multipass = true;
+  *out = plan;
+  return FWR_OK;
+}
+
+}  // namespace

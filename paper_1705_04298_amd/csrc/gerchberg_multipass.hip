@@ -1,0 +1,376 @@
+// Multi-pass Gerchberg extension + Fourier reconstruction for grids too large
+// for one workgroup's LDS (N = 256: 512 KiB per frame pair).
+//
+// Same formulation as the on-chip kernel (two frames per complex field; the
+// loop step is q = G^T s, phi = TF^-1[TF(q) / |G|^2], s' = G phi; see
+// gerchberg_onchip.hip), split into grid-wide phases that exchange whole
+// fields through HBM (the 32 MiB working set of 64 frame pairs stays in the
+// MALL):
+//   row_fwd  : stencil (or F0 at the start) on 16-row blocks + forward row FFTs  -> SPEC
+//   col      : forward column FFTs, filter, inverse column FFTs on 16-column tiles (in place)
+//   row_inv  : inverse row FFTs -> PHI
+// and, once per call, the explicit final step (cell slopes, Eq. 5 sums and
+// fix, scatter to q) and the output kernels.
+//
+// FFT of a 256-point line: 16 threads, 16 x 16 decomposition through LDS.
+// Stage A: thread r takes points 16a + r, DFT-16 over a, twiddle W_256^(r k1);
+// stage B: thread k1 takes the 16 contiguous results, DFT-16.  Position
+// 16 k1 + k2 then holds frequency k1 + 16 k2 (digit-reversed); the filter
+// table is laid out in that order and the inverse undoes it.  Lines are
+// padded by one element every 16 (272 per line) to spread LDS banks.
+#include "fft_lane.h"
+#include "multipass.h"
+
+namespace fwr {
+
+namespace mp {
+
+constexpr int NN = 256;
+constexpr int R = 16;
+constexpr int LP = NN + NN / R;  // padded line length (complex)
+constexpr int THREADS = 256;
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// 256-point line FFT in LDS (L = padded line), thread r = 0..15 of the line's 16.
+// The caller separates stages with workgroup barriers (all lines of a block
+// are transformed together).
+template <int DIR>
+__device__ __forceinline__ void fft_stage_a(float2 *L, int r, const float2 *tw) {
+  float2 v[R];
+  if constexpr (DIR < 0) {
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = L[pad(R * a + r)];
+    dft<R, -1>(v);
+#pragma unroll
+    for (int k = 1; k < R; ++k) v[k] = cmul(v[k], tw[(r * k) & (NN - 1)]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) L[pad(R * k + r)] = v[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = L[pad(R * k + r)];
+#pragma unroll
+    for (int k = 1; k < R; ++k) v[k] = cmul_conj(v[k], tw[(r * k) & (NN - 1)]);
+    dft<R, +1>(v);
+#pragma unroll
+    for (int a = 0; a < R; ++a) L[pad(R * a + r)] = v[a];
+  }
+}
+template <int DIR>
+__device__ __forceinline__ void fft_stage_b(float2 *L, int r) {
+  float2 v[R];
+#pragma unroll
+  for (int b = 0; b < R; ++b) v[b] = L[pad(R * r + b)];
+  dft<R, DIR>(v);
+#pragma unroll
+  for (int b = 0; b < R; ++b) L[pad(R * r + b)] = v[b];
+}
+
+__device__ __forceinline__ size_t field(int pair) { return (size_t)pair * NN * NN; }
+
+__device__ __forceinline__ void load_tw(float2 *tw, const float2 *g, int t) {
+  tw[t] = g[t];  // 256 entries, 256 threads
+}
+
+// in-pupil test of cell (cm, cn) (indices mod N)
+__device__ __forceinline__ bool in_pupil(const uint8_t *mask, int n, int o, int cm, int cn) {
+  cm &= NN - 1;
+  cn &= NN - 1;
+  const unsigned i = unsigned(cm - o), j = unsigned(cn - o);
+  return i < unsigned(n) && j < unsigned(n) && mask[i * n + j] != 0;
+}
+
+// measured (s_x, s_y) of cell (cm, cn) for frames A (real) and B (imag)
+__device__ __forceinline__ void measured(const MPArgs &a, int pair, int cm, int cn, float2 &sx, float2 &sy) {
+  const int n = a.n, plane = n * n;
+  const int idx = (cm - a.o) * n + (cn - a.o);
+  const float *sa = a.slopes + (size_t)(2 * pair) * 2 * plane;
+  const bool hasB = 2 * pair + 1 < a.B;
+  sx = make_float2(sa[idx], hasB ? sa[2 * plane + idx] : 0.f);
+  sy = make_float2(sa[plane + idx], hasB ? sa[3 * plane + idx] : 0.f);
+}
+
+// ---------------------------------------------------------------- row phase
+// mode 0: q2 = F0 (start of the loop; also stores F0 rows of the window)
+// mode 1: q2 = F0 + sum over out-of-pupil cells of (phi - phi_diagonal)
+__global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
+  __shared__ float2 ph[(R + 2) * NN];  // phi rows m0-1 .. m0+16
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl;
+  load_tw(tw, a.tw256, t);
+  if (mode == 1) {
+    const float2 *P = a.phi + field(pair);
+    for (int i = t; i < (R + 2) * NN; i += THREADS) {
+      const int row = (m0 - 1 + i / NN) & (NN - 1);
+      ph[i] = P[(size_t)row * NN + (i % NN)];
+    }
+  }
+  __syncthreads();
+  const bool win_row = m >= a.o && m <= a.o + a.n;
+  float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
+#pragma unroll 4
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q;
+    float2 f = make_float2(0.f, 0.f);
+    if (mode == 0) {
+      if (win_row) {
+        const int nl = (nn - 1) & (NN - 1), up = (m - 1) & (NN - 1);
+        float2 sx, sy;
+        if (in_pupil(a.mask, a.n, a.o, m, nn)) { measured(a, pair, m, nn, sx, sy); f = csub(f, cadd(sx, sy)); }
+        if (in_pupil(a.mask, a.n, a.o, up, nl)) { measured(a, pair, up, nl, sx, sy); f = cadd(f, cadd(sx, sy)); }
+        if (in_pupil(a.mask, a.n, a.o, m, nl)) { measured(a, pair, m, nl, sx, sy); f = cadd(f, csub(sx, sy)); }
+        if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
+        F0[(size_t)(m - a.o) * NN + nn] = f;
+      }
+    } else {
+      if (win_row) f = F0[(size_t)(m - a.o) * NN + nn];
+      const uint8_t c = a.codes[m * NN + nn];
+      const float2 p0 = ph[(rl + 1) * NN + nn];
+      const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
+      const float2 d1 = ph[(rl + 2) * NN + np], d2 = ph[rl * NN + nm];
+      const float2 d3 = ph[(rl + 2) * NN + nm], d4 = ph[rl * NN + np];
+      if (c & 1) f = cadd(f, csub(p0, d1));
+      if (c & 2) f = cadd(f, csub(p0, d2));
+      if (c & 4) f = cadd(f, csub(p0, d3));
+      if (c & 8) f = cadd(f, csub(p0, d4));
+    }
+    L[rl * LP + pad(nn)] = f;
+  }
+  __syncthreads();
+  fft_stage_a<-1>(L + rl * LP, r, tw);
+  __syncthreads();
+  fft_stage_b<-1>(L + rl * LP, r);
+  __syncthreads();
+  float2 *S = a.spec + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / NN, p = i % NN;
+    S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+  }
+}
+
+// ---------------------------------------------------------------- column phase
+__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, cl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, c0 = blockIdx.x * R;
+  load_tw(tw, a.tw256, t);
+  float2 *S = a.spec + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / R, cc = i % R;
+    L[cc * LP + pad(row)] = S[(size_t)row * NN + c0 + cc];
+  }
+  __syncthreads();
+  fft_stage_a<-1>(L + cl * LP, r, tw);
+  __syncthreads();
+  fft_stage_b<-1>(L + cl * LP, r);
+  __syncthreads();
+  const float *hc = h + (size_t)(c0 + cl) * NN;
+#pragma unroll 4
+  for (int q = 0; q < R; ++q) {
+    const int p = r + R * q;
+    float2 v = L[cl * LP + pad(p)];
+    const float hv = hc[p];
+    L[cl * LP + pad(p)] = make_float2(v.x * hv, v.y * hv);
+  }
+  __syncthreads();
+  fft_stage_b<+1>(L + cl * LP, r);
+  __syncthreads();
+  fft_stage_a<+1>(L + cl * LP, r, tw);
+  __syncthreads();
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / R, cc = i % R;
+    S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
+  }
+}
+
+// ---------------------------------------------------------------- inverse rows
+__global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = blockIdx.x * R;
+  load_tw(tw, a.tw256, t);
+  const float2 *S = a.spec + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / NN, p = i % NN;
+    L[row * LP + pad(p)] = S[(size_t)(m0 + row) * NN + p];
+  }
+  __syncthreads();
+  fft_stage_b<+1>(L + rl * LP, r);
+  __syncthreads();
+  fft_stage_a<+1>(L + rl * LP, r, tw);
+  __syncthreads();
+  float2 *Ph = a.phi + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / NN, p = i % NN;
+    Ph[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+  }
+}
+
+// ---------------------------------------------------------------- final step
+// cell slopes: measured inside the pupil (bit for bit), G phi outside; row sums R_m
+__global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero) {
+  __shared__ float2 ph[(R + 1) * NN];
+  __shared__ float2 part[THREADS];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl;
+  const float2 *P = a.phi + field(pair);
+  for (int i = t; i < (R + 1) * NN; i += THREADS) {
+    const int row = (m0 + i / NN) & (NN - 1);
+    ph[i] = phi_zero ? make_float2(0.f, 0.f) : P[(size_t)row * NN + (i % NN)];
+  }
+  __syncthreads();
+  float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
+  float2 acc = make_float2(0.f, 0.f);
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q, np = (nn + 1) & (NN - 1);
+    float2 sx, sy;
+    if (in_pupil(a.mask, a.n, a.o, m, nn)) {
+      measured(a, pair, m, nn, sx, sy);
+    } else {
+      const float2 a0 = ph[rl * NN + nn], b = ph[rl * NN + np];
+      const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
+      sx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
+      sy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
+    }
+    SX[(size_t)m * NN + nn] = sx;
+    SY[(size_t)m * NN + nn] = sy;
+    acc = cadd(acc, sx);
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (r == 0) {  // fixed-order row sum
+    float2 s = make_float2(0.f, 0.f);
+    for (int i = 0; i < R; ++i) s = cadd(s, part[rl * R + i]);
+    a.sums[(size_t)pair * 2 * NN + NN + m] = s;
+  }
+}
+
+// column sums C_n (fixed order), then Eq. 5 on column N-1 of s_x and row N-1 of s_y
+__global__ __launch_bounds__(THREADS) void periodic_kernel(MPArgs a) {
+  const int pair = blockIdx.x, t = threadIdx.x;
+  float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
+  float2 *sums = a.sums + (size_t)pair * 2 * NN;
+  float2 cs = make_float2(0.f, 0.f);
+  for (int m = 0; m < NN; ++m) cs = cadd(cs, SY[(size_t)m * NN + t]);
+  __syncthreads();  // all column reads done before row N-1 changes
+  SY[(size_t)(NN - 1) * NN + t] = csub(SY[(size_t)(NN - 1) * NN + t], cs);
+  SX[(size_t)t * NN + NN - 1] = csub(SX[(size_t)t * NN + NN - 1], sums[NN + t]);
+}
+
+// extended slopes out: frame A from the real parts, frame B from the imaginary parts
+__global__ __launch_bounds__(THREADS) void ext_out_kernel(MPArgs a) {
+  const int pair = blockIdx.y, m = blockIdx.x, t = threadIdx.x;
+  const float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
+  const size_t plane = (size_t)NN * NN;
+  float *oa = a.out + (size_t)(2 * pair) * 2 * plane;
+  const bool hasB = 2 * pair + 1 < a.B;
+  const size_t idx = (size_t)m * NN + t;
+  const float2 x = SX[idx], y = SY[idx];
+  oa[idx] = x.x;
+  oa[plane + idx] = y.x;
+  if (hasB) {
+    oa[2 * plane + idx] = x.y;
+    oa[3 * plane + idx] = y.y;
+  }
+}
+
+// q2 = -p(m,n) + p(m-1,n-1) + r(m,n-1) - r(m-1,n), p = s_x + s_y, r = s_x - s_y; row FFT
+__global__ __launch_bounds__(THREADS) void scatter_kernel(MPArgs a) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl, up = (m - 1) & (NN - 1);
+  load_tw(tw, a.tw256, t);
+  const float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q, nm = (nn - 1) & (NN - 1);
+    const float2 p_mn = cadd(SX[(size_t)m * NN + nn], SY[(size_t)m * NN + nn]);
+    const float2 p_ul = cadd(SX[(size_t)up * NN + nm], SY[(size_t)up * NN + nm]);
+    const float2 r_ml = csub(SX[(size_t)m * NN + nm], SY[(size_t)m * NN + nm]);
+    const float2 r_un = csub(SX[(size_t)up * NN + nn], SY[(size_t)up * NN + nn]);
+    L[rl * LP + pad(nn)] = cadd(csub(p_ul, p_mn), csub(r_ml, r_un));
+  }
+  __syncthreads();
+  fft_stage_a<-1>(L + rl * LP, r, tw);
+  __syncthreads();
+  fft_stage_b<-1>(L + rl * LP, r);
+  __syncthreads();
+  float2 *S = a.spec + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / NN, p = i % NN;
+    S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+  }
+}
+
+// (n+1) x (n+1) node window of phi
+__global__ __launch_bounds__(THREADS) void phase_out_kernel(MPArgs a) {
+  const int pair = blockIdx.y, i = blockIdx.x;  // window row
+  const int n1 = a.n + 1;
+  const float2 *P = a.phi + field(pair);
+  float *oa = a.out + (size_t)(2 * pair) * n1 * n1;
+  const bool hasB = 2 * pair + 1 < a.B;
+  for (int j = threadIdx.x; j < n1; j += THREADS) {
+    const float2 v = P[(size_t)(a.o + i) * NN + a.o + j];
+    oa[(size_t)i * n1 + j] = v.x;
+    if (hasB) oa[(size_t)n1 * n1 + (size_t)i * n1 + j] = v.y;
+  }
+}
+
+}  // namespace mp
+
+size_t multipass_workspace_bytes(int N, int n, int max_batch) {
+  if (N != mp::NN) return 0;
+  const size_t pairs = (size_t)(max_batch + 1) / 2;
+  const size_t f = (size_t)N * N * sizeof(float2);
+  return pairs * (4 * f + (size_t)(n + 1) * N * sizeof(float2) + 2 * (size_t)N * sizeof(float2));
+}
+
+bool multipass_supported(int N) { return N == mp::NN; }
+
+hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
+  using namespace mp;
+  MPArgs a = a0;
+  const int pairs = (a.B + 1) / 2;
+  const dim3 rows(NN / R, pairs), blk(THREADS);
+  const bool periodic = (a.flags & kMPPeriodic) != 0;
+  const bool each = (a.flags & kMPPeriodicEach) != 0;
+  const bool explicit_final = periodic || extend || (each && a.n_iter > 0);
+  const bool fix_final = periodic || (each && a.n_iter > 0);
+  auto explicit_q = [&](bool phi_zero, bool fix) {
+    hipLaunchKernelGGL(slopes_kernel, rows, blk, 0, s, a, phi_zero ? 1 : 0);
+    if (fix) hipLaunchKernelGGL(periodic_kernel, dim3(pairs), blk, 0, s, a);
+  };
+  // start: q2 = F0 (also fills the F0 rows), forward row FFTs
+  hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 0);
+  for (int it = 0; it < a.n_iter; ++it) {
+    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_loop);
+    hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
+    if (it == a.n_iter - 1) break;
+    if (each) {
+      explicit_q(false, true);
+      hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
+    } else {
+      hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 1);
+    }
+  }
+  if (explicit_final) {
+    explicit_q(a.n_iter == 0, fix_final);
+    if (extend) {
+      hipLaunchKernelGGL(ext_out_kernel, dim3(NN, pairs), blk, 0, s, a);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
+  } else if (a.n_iter > 0) {
+    hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 1);
+  }
+  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final);
+  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
+  hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fwr

@@ -34,6 +34,12 @@
 
 #include <cstdint>
 
+// Minimum waves per SIMD the register allocation must allow for N <= 80 (2: one
+// workgroup of 5 waves per CU, up to 256 VGPRs; 3: two workgroups, <= 168 VGPRs).
+#ifndef FWR_ONCHIP_MIN_WAVES
+#define FWR_ONCHIP_MIN_WAVES 2
+#endif
+
 namespace fwr {
 
 template <int N>
@@ -47,7 +53,11 @@ struct Onchip {
   // registers (one workgroup per CU).
   static constexpr bool F0_IN_LDS = N <= 80;
   static constexpr int STATIC_LDS_BYTES = (TILE + 2 * N + T * 4) * 8;
-  static int lds_bytes(int n) { return STATIC_LDS_BYTES + (F0_IN_LDS ? (n + 1) * N * 8 : 0); }
+  static int lds_bytes(int n) { return STATIC_LDS_BYTES + (F0_IN_LDS ? (n + 1) * PITCH * 8 : 0); }
+  // Register budget: two workgroups per CU (80 KB of LDS each at N = 80) put
+  // three waves on some SIMDs, i.e. at most 168 VGPRs.  The iteration loop fits
+  // without spills; the once-per-frame final step spills a few values.
+  static constexpr int WAVES_PER_SIMD = N <= 80 ? FWR_ONCHIP_MIN_WAVES : 2;
 };
 
 // c ? a : b on the bit patterns: exact, and both operands are always computed, so
@@ -58,14 +68,16 @@ __device__ __forceinline__ float select_bits(bool c, float a, float b) {
 }
 
 template <int N, bool EACH>
-__global__ __launch_bounds__(Onchip<N>::THREADS) void gerchberg_onchip_kernel(OnchipArgs a) {
+__global__ __launch_bounds__(Onchip<N>::THREADS)
+__attribute__((amdgpu_waves_per_eu(Onchip<N>::WAVES_PER_SIMD)))
+void gerchberg_onchip_kernel(OnchipArgs a) {
   using C = Onchip<N>;
   constexpr int T = C::T;
   constexpr int P = C::PITCH;
   __shared__ float2 buf[C::TILE];
   __shared__ float2 sums[2 * N];  // Eq. 5: column sums C_n, then row sums R_m
   __shared__ float2 tw[T * 4];
-  extern __shared__ float2 f0rows[];  // [(n+1)][N], lane-blocked like the tile rows
+  extern __shared__ float2 f0rows[];  // [(n+1)][PITCH], lane-blocked like the tile rows
 
   const int t = threadIdx.x;
   const int line = t >> 2;
@@ -123,10 +135,10 @@ __global__ __launch_bounds__(Onchip<N>::THREADS) void gerchberg_onchip_kernel(On
   if constexpr (C::F0_IN_LDS) {
     if (in_rows) {
 #pragma unroll
-      for (int k = 0; k < T; ++k) f0rows[(line - o) * N + T * j + k] = f0[k];
+      for (int k = 0; k < T; ++k) f0rows[(line - o) * P + T * j + k] = f0[k];
     }
   }
-  const int f0row = (in_rows ? line - o : 0) * N + T * j;
+  const int f0row = (in_rows ? line - o : 0) * P + T * j;
   const float rowf = in_rows ? 1.f : 0.f;
 
   // neighbour column slots for n + 1 and n - 1 (lane-blocked layout)
@@ -381,7 +393,7 @@ __global__ __launch_bounds__(Onchip<N>::THREADS) void gerchberg_onchip_kernel(On
 template <int N>
 hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s) {
   const int groups = (a.B + 1) / 2;
-  const size_t dyn = Onchip<N>::F0_IN_LDS ? size_t(a.n + 1) * N * 8 : 0;
+  const size_t dyn = Onchip<N>::F0_IN_LDS ? size_t(a.n + 1) * Onchip<N>::PITCH * 8 : 0;
   if (a.flags & kFlagPeriodicEach)
     hipLaunchKernelGGL((gerchberg_onchip_kernel<N, true>), dim3(groups), dim3(Onchip<N>::THREADS), dyn, s, a);
   else
@@ -392,7 +404,7 @@ hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s) {
 template <int N>
 hipError_t prepare_onchip(int n) {
   // dynamic LDS above the default 64 KiB window must be requested explicitly
-  const int dyn = Onchip<N>::F0_IN_LDS ? (n + 1) * N * 8 : 0;
+  const int dyn = Onchip<N>::F0_IN_LDS ? (n + 1) * Onchip<N>::PITCH * 8 : 0;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   if (e == hipSuccess)

@@ -1,0 +1,32 @@
+// Launch interface of the multi-pass (grid through HBM) Gerchberg path, N = 256.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fwr {
+
+enum : int { kMPPeriodic = 1, kMPPeriodicEach = 2 };
+
+struct MPArgs {
+  const float *slopes;   // [B][2][n][n]
+  float *out;            // [B][n+1][n+1] or [B][2][N][N]
+  // workspace, per frame pair: four N x N complex fields, the forcing rows and the sums
+  float2 *phi, *spec, *sx, *sy;
+  float2 *f0;            // [pairs][n+1][N]
+  float2 *sums;          // [pairs][2N]: C_n then R_m
+  const float *h_loop;   // [N][N], column position major, digit-reversed positions
+  const float *h_final;
+  const float2 *tw256;   // W_256^e, e = 0..255
+  const uint8_t *mask;   // [n][n]
+  const uint8_t *codes;  // [N][N]: out-of-pupil bits of the 4 cells around each node
+  int B, n, o, n_iter, flags;
+};
+
+bool multipass_supported(int N);
+size_t multipass_workspace_bytes(int N, int n, int max_batch);
+hipError_t multipass_run(const MPArgs &a, bool extend, hipStream_t s);
+
+}  // namespace fwr

@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfwr.so")
+# FWR_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("FWR_LIBRARY") or os.path.join(_HERE, "libfwr.so")
 
 FWR_OK = 0
 FWR_E_INVAL = -1

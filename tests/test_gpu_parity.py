@@ -96,9 +96,11 @@ def test_lsq_final_filter(fwr):
 
 
 @pytest.mark.parametrize("N,n", [(8, 4), (8, 6), (12, 6), (16, 8), (16, 2), (20, 10), (24, 12),
-                                 (32, 16), (40, 20), (48, 24), (64, 32), (80, 78), (128, 64)])
+                                 (32, 16), (40, 20), (48, 24), (64, 32), (80, 78), (128, 64),
+                                 (256, 128), (256, 250)])
 def test_grid_sizes(fwr, N, n):
-    """Every on-chip grid size, random masks, white slopes; includes n = N - 2 (thin border)."""
+    """Every grid size (on-chip N <= 128, multi-pass N = 256), random masks, white slopes;
+    includes n = N - 2 (thin border)."""
     mask = I.random_mask(n, seed=N * 1000 + n)
     slopes = I.random_slopes(3, n, seed=N + n)
     p = O.Params(n_sub=n, n_grid=N, n_iter=6, periodic=True, gamma=1.0, noise_var=0.01, r0=0.15,
@@ -180,7 +182,7 @@ def test_abi_errors(fwr):
     with pytest.raises(F.FwrError):
         F.Plan(40, 40, mask)          # N <= n
     with pytest.raises(F.FwrError) as e:
-        F.Plan(40, 84, mask)          # not an on-chip size
+        F.Plan(40, 84, mask)          # not a supported grid size
     assert e.value.status == F.FWR_E_UNSUPPORTED
 
 
@@ -201,3 +203,33 @@ def test_full_batch_sampled(fwr):
     for b in rng.choice(B, 12, replace=False):
         want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
         assert rel_rms(got[b], want) <= REL_TOL, b
+
+
+ELT = dict(n_sub=128, n_grid=256, d=39.0 / 128, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
+
+
+@pytest.mark.parametrize("n_iter,periodic,each", [(20, True, False), (0, True, False), (3, False, False),
+                                                  (2, True, True)])
+def test_elt128_multipass(fwr, n_iter, periodic, each):
+    """128x128 subapertures, D = 39 m, padded to 256x256 (multi-pass through HBM)."""
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, 3, dtype=np.float64)
+    check_reconstruct(fwr, slopes, mask,
+                      O.Params(n_iter=n_iter, periodic=periodic, periodic_each_iter=each, **ELT), "elt")
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_elt128_extend(fwr, periodic):
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, 2, start=5, dtype=np.float32)
+    p = O.Params(n_iter=6, periodic=periodic, **ELT)
+    _flush(f"[gpu] elt extend periodic={periodic}")
+    got = run_case(fwr, slopes, mask, p, what="extend")
+    o = 64
+    m = mask.astype(bool)
+    for b in range(2):
+        ref = O.extend(slopes[b].astype(np.float64), mask, p)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(got[b, 0] - ref.sx).max() <= 10 * REL_TOL * scale
+        assert np.abs(got[b, 1] - ref.sy).max() <= 10 * REL_TOL * scale
+        assert np.array_equal(got[b, 0, o:o + 128, o:o + 128][m].astype(np.float32), slopes[b, 0][m])
