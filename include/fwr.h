@@ -117,6 +117,56 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream);
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes);
 
+/* ------------------------------------------------------------------------
+ * Start values and residual (used by the learned initial extension).
+ *
+ * Algorithm 1 starts from the measurement padded with zeros (Sec. 4.1).  These
+ * variants start from `d_start` (float[B][2][N][N], slopes on the padded grid)
+ * outside the pupil instead; inside the pupil the measurement is used as
+ * always.  `d_resid` (float[B], may be NULL) receives the in-pupil misfit of
+ * the last iteration, ||P (G phi - s0)|| / ||P s0|| (0 when n_iter = 0 or the
+ * pupil is empty).  On-chip grids only (N <= 128); FWR_E_UNSUPPORTED otherwise.
+ */
+fwr_status fwr_extend_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_ext,
+                            float *d_resid, int32_t B);
+fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_phase,
+                                 float *d_resid, int32_t B);
+
+/* ------------------------------------------------------------------------
+ * Learned initial extension (not part of the paper's method).
+ *
+ * A seven-layer 3x3 CNN (channels 3-32-32-32-32-32-32-2, ReLU after all but
+ * the last layer, zero "same" padding) maps (padded x slopes, padded y slopes,
+ * pupil indicator) on the N x N grid to x and y slopes on the whole grid; its
+ * values outside the pupil start Algorithm 1 (fwr_*_start).  BF16 weights and
+ * activations, FP32 accumulation (MFMA), FP32 master weights and Adam state.
+ * Inputs are scaled by `input_scale` before the network and outputs divided by
+ * it.  Parameters use the layout: for each layer, weights [out][in][3][3] then
+ * biases [out], float32, 47714 values in total.
+ */
+typedef struct fwr_cnn_s *fwr_cnn_t;
+
+/* mask: HOST n*n valid-subaperture bytes (as for fwr_plan); N*N must be a
+ * multiple of 64.  training = 0 keeps two activation buffers (inference);
+ * training = 1 keeps every layer's activations and gradient buffers.  Weights
+ * start at zero: call fwr_cnn_set_params. */
+fwr_status fwr_cnn_create(int32_t n_sub, int32_t n_grid, const uint8_t *mask, int32_t max_batch, float input_scale,
+                          int32_t training, void *stream, fwr_cnn_t *out);
+/* HOST parameter arrays of `count` = 47714 floats. set resets the Adam state. */
+fwr_status fwr_cnn_set_params(fwr_cnn_t cnn, const float *h_params, int32_t count);
+fwr_status fwr_cnn_get_params(fwr_cnn_t cnn, float *h_params, int32_t count);
+/* d_slopes: float[B][2][n][n]; d_pred: float[B][2][N][N] predicted slopes. */
+fwr_status fwr_cnn_forward(fwr_cnn_t cnn, const float *d_slopes, float *d_pred, int32_t B);
+/* After fwr_cnn_forward on the same batch (training mode): loss = mean over the
+ * out-of-pupil cells of both channels of (scaled prediction - scaled target)^2,
+ * gradients of every parameter into the plan's gradient buffer; *h_loss (may be
+ * NULL) receives the loss (the call then waits for the stream). */
+fwr_status fwr_cnn_backward(fwr_cnn_t cnn, const float *d_pred, const float *d_target, int32_t B, float *h_loss);
+fwr_status fwr_cnn_get_grads(fwr_cnn_t cnn, float *h_grads, int32_t count);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
+fwr_status fwr_cnn_adam_step(fwr_cnn_t cnn, float lr);
+fwr_status fwr_cnn_destroy(fwr_cnn_t cnn);
+
 /* Static description of a status code (never NULL). */
 const char *fwr_status_string(int32_t status);
 

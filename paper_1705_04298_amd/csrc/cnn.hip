@@ -1,0 +1,322 @@
+// Learned initial extension: a 7-layer 3x3 CNN in BF16 on MFMA (FP32 accumulate).
+//
+// Activations are NHWC bf16 ([B][N][N][C], C = 8, 16 or 32; padded channels are 0).
+// A convolution is an implicit GEMM: M = pixels, N = output channels,
+// K = (tap, input channel), tap-major, so that 8 consecutive K values of one
+// lane are 8 consecutive channels of one neighbour pixel (one 16-byte load).
+// v_mfma_f32_16x16x32_bf16 operand layout (lane l of 64):
+//   A (16 x 32): row l % 16, k = 8 (l / 16) .. + 7
+//   B (32 x 16): column l % 16, k = 8 (l / 16) .. + 7
+//   C (16 x 16): column l % 16, rows 4 (l / 16) .. + 3
+// Backward-data is the same kernel on the output gradient with the weights
+// transposed and the taps flipped; the weight gradient is a GEMM over pixels,
+// staged through LDS in channel-major (transposed) form.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cnn.h"
+
+namespace fwr {
+namespace cnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+template <int CIN>
+constexpr int kpad() { return ((9 * CIN + 31) / 32) * 32; }
+
+// ------------------------------------------------------------------ forward / backward-data
+// MODE 0: y = relu(conv + bias) -> bf16 NHWC [.., 32]
+// MODE 1: y = (conv + bias) * out_scale for channels 0, 1 -> fp32 planar [B][2][N][N]
+// MODE 2: y = conv * (act[p][c] > 0) -> bf16 NHWC [.., COUT] (gradient through the ReLU)
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ x, const uint16_t *__restrict__ wt,
+                                                   const float *__restrict__ bias, void *out,
+                                                   const uint16_t *__restrict__ act, int npix, int N,
+                                                   float out_scale) {
+  constexpr int K = kpad<CIN>(), KCH = K / 32, NT = COUT / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int base = (blockIdx.x * 4 + wave) * 64;  // 64 pixels per wave; N*N is a multiple of 64
+  if (base >= npix) return;
+  const int col = lane & 15, kq = lane >> 4;
+  bf16x8 bw[KCH][NT];
+#pragma unroll
+  for (int kc = 0; kc < KCH; ++kc)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bw[kc][nt] = load8(wt + (size_t)(nt * 16 + col) * K + kc * 32 + 8 * kq);
+  const int NN = N * N;
+#pragma unroll 1
+  for (int mt = 0; mt < 4; ++mt) {
+    const int p = base + mt * 16 + col;  // A row of this lane
+    const int f = p / NN, rem = p - f * NN, y = rem / N, xx = rem - y * N;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KCH; ++kc) {
+      const int k0 = kc * 32 + 8 * kq;
+      const int t = k0 / CIN, c0 = k0 - t * CIN;
+      const int yy = y + t / 3 - 1, xs = xx + t % 3 - 1;
+      bf16x8 a = zero8();
+      if (t < 9 && yy >= 0 && yy < N && xs >= 0 && xs < N)
+        a = load8(x + ((size_t)f * NN + (size_t)yy * N + xs) * CIN + c0);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[kc][nt], acc[nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int c = nt * 16 + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = base + mt * 16 + 4 * kq + i;  // output pixel of acc[nt][i]
+        float v = acc[nt][i];
+        if constexpr (MODE == 0) {
+          v = fmaxf(v + bias[c], 0.f);
+          static_cast<uint16_t *>(out)[(size_t)q * COUT + c] = f2bf(v);
+        } else if constexpr (MODE == 1) {
+          if (c < 2) {
+            const int fq = q / NN, rq = q - fq * NN;
+            static_cast<float *>(out)[((size_t)fq * 2 + c) * NN + rq] = (v + bias[c]) * out_scale;
+          }
+        } else {
+          const float g = bf2f(act[(size_t)q * COUT + c]) > 0.f ? v : 0.f;
+          static_cast<uint16_t *>(out)[(size_t)q * COUT + c] = f2bf(g);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ weight gradient
+// dW[co][t*CIN + ci] += sum_p dz[p][co] x[p + off(t)][ci]; one block per frame, 32-pixel chunks.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dz,
+                                                    float *__restrict__ dw, float *__restrict__ db, int N) {
+  constexpr int NCOL = 9 * CIN, MT = COUT / 16, NTT = (NCOL + 15) / 16, TILES = MT * NTT;
+  constexpr int PER_WAVE = (TILES + 3) / 4;
+  __shared__ __attribute__((aligned(16))) uint16_t dzt[COUT][32 + 8];      // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t xt[NTT * 16][32 + 8];   // [(t, ci)][pixel], rows >= NCOL zero
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+  const int col = lane & 15, kq = lane >> 4;
+  const int f = blockIdx.x, NN = N * N;
+  const uint16_t *xf = x + (size_t)f * NN * CIN;
+  const uint16_t *dzf = dz + (size_t)f * NN * COUT;
+  f32x4 acc[PER_WAVE];
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;  // bias gradient partial of channel t (t < COUT)
+  for (int i = t; i < (NTT * 16 - NCOL) * 40; i += 256) xt[NCOL + i / 40][i % 40] = 0;
+  for (int p0 = 0; p0 < NN; p0 += 32) {
+    __syncthreads();
+    for (int i = t; i < 32 * COUT; i += 256) {
+      const int pp = i / COUT, c = i - pp * COUT;
+      dzt[c][pp] = dzf[(size_t)(p0 + pp) * COUT + c];
+    }
+    for (int i = t; i < 32 * NCOL; i += 256) {
+      const int pp = i / NCOL, r = i - pp * NCOL, tap = r / CIN, c = r - tap * CIN;
+      const int p = p0 + pp, y = p / N, xx = p - y * N;
+      const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
+      xt[r][pp] = (yy >= 0 && yy < N && xs >= 0 && xs < N) ? xf[((size_t)yy * N + xs) * CIN + c] : uint16_t(0);
+    }
+    __syncthreads();
+    if (t < COUT)
+      for (int pp = 0; pp < 32; ++pp) bsum += bf2f(dzt[t][pp]);
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) {
+      const int tile = wave * PER_WAVE + i;
+      if (tile < TILES) {
+        const int mt = tile / NTT, nt = tile - mt * NTT;
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&dzt[mt * 16 + col][8 * kq]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xt[nt * 16 + col][8 * kq]);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) {
+    const int tile = wave * PER_WAVE + i;
+    if (tile < TILES) {
+      const int mt = tile / NTT, nt = tile - mt * NTT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = mt * 16 + 4 * kq + r, k = nt * 16 + col;
+        if (k < NCOL) atomicAdd(&dw[(size_t)co * NCOL + k], acc[i][r]);
+      }
+    }
+  }
+  if (t < COUT) atomicAdd(&db[t], bsum);
+}
+
+// ------------------------------------------------------------------ features, loss, Adam
+// feat[b][m][n][0..7] = (s0x * scale, s0y * scale, P, 0, ...) on the N x N grid
+__global__ void features_kernel(const float *__restrict__ slopes, const uint8_t *__restrict__ mask,
+                                uint16_t *__restrict__ feat, int B, int n, int N, float scale) {
+  const size_t total = (size_t)B * N * N;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int b = int(i / ((size_t)N * N));
+  const int rem = int(i - (size_t)b * N * N), m = rem / N, c = rem - m * N, o = (N - n) / 2;
+  float sx = 0.f, sy = 0.f, pv = 0.f;
+  const int ii = m - o, jj = c - o;
+  if (ii >= 0 && ii < n && jj >= 0 && jj < n && mask[ii * n + jj]) {
+    const float *sb = slopes + (size_t)b * 2 * n * n;
+    sx = sb[ii * n + jj] * scale;
+    sy = sb[n * n + ii * n + jj] * scale;
+    pv = 1.f;
+  }
+  uint16_t *fp = feat + i * 8;
+  fp[0] = f2bf(sx);
+  fp[1] = f2bf(sy);
+  fp[2] = f2bf(pv);
+#pragma unroll
+  for (int k = 3; k < 8; ++k) fp[k] = 0;
+}
+
+// dz7[p][c] = 2 (pred_raw - target * scale) * outside / count  (c < 2; channels 2..15 zero);
+// pred is in slope units (pred_raw / scale); loss accumulates sum(diff^2) / count
+__global__ void loss_grad_kernel(const float *__restrict__ pred, const float *__restrict__ target,
+                                 const uint8_t *__restrict__ mask, uint16_t *__restrict__ dz7,
+                                 float *__restrict__ loss, int B, int n, int N, float scale, float inv_count) {
+  const size_t total = (size_t)B * N * N;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (i < total) {
+    const int b = int(i / ((size_t)N * N));
+    const int rem = int(i - (size_t)b * N * N), m = rem / N, c = rem - m * N, o = (N - n) / 2;
+    const int ii = m - o, jj = c - o;
+    const bool inside = ii >= 0 && ii < n && jj >= 0 && jj < n && mask[ii * n + jj];
+    uint16_t *g = dz7 + i * 16;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g[k] = 0;
+    if (!inside) {
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) {
+        const size_t idx = ((size_t)b * 2 + ch) * N * N + rem;
+        const float d = (pred[idx] - target[idx]) * scale;
+        l += d * d;
+        g[ch] = f2bf(2.f * d * inv_count);
+      }
+    }
+  }
+  // wave reduction then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, l * inv_count);
+}
+
+// Adam on FP32 master weights (kernel layout [co][t][ci]), then the bf16 copies:
+// wt [co][kpad] for the forward pass, wtb [ci][t' * COUTS + co] (taps flipped) for backward-data.
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m1,
+                            float *__restrict__ m2, int count, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  w[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+// master weights (fp32 [cout_s][9][cin_s], padded channels 0) -> bf16 forward layout
+// wt [cout_s][kpad_f] (k = t * cin_s + ci) and flipped backward-data layout
+// wtb [cin_s][kpad_b] (k = t' * cout_s + co, weight w[co][8 - t'][ci])
+__global__ void pack_kernel(const float *__restrict__ w, uint16_t *__restrict__ wt, uint16_t *__restrict__ wtb,
+                            int cin_s, int cout_s, int kpad_f, int kpad_b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cout_s * kpad_f) {
+    const int co = i / kpad_f, k = i - co * kpad_f, t = k / cin_s, ci = k - t * cin_s;
+    wt[i] = f2bf(t < 9 ? w[((size_t)co * 9 + t) * cin_s + ci] : 0.f);
+  }
+  if (wtb && i < cin_s * kpad_b) {
+    const int ci = i / kpad_b, k = i - ci * kpad_b, t = k / cout_s, co = k - t * cout_s;
+    wtb[i] = f2bf(t < 9 ? w[((size_t)co * 9 + (8 - t)) * cin_s + ci] : 0.f);
+  }
+}
+
+}  // namespace cnn
+
+// ------------------------------------------------------------------ host-side launchers
+namespace cnn_launch {
+using namespace cnn;
+
+hipError_t conv(int layer, const uint16_t *x, const uint16_t *wt, const float *bias, void *out, int B, int N,
+                float out_scale, hipStream_t s) {
+  const int npix = B * N * N;
+  const dim3 grid((npix + 255) / 256), blk(256);
+  if (layer == 0)
+    hipLaunchKernelGGL((conv_kernel<8, 32, 0>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, 1.f);
+  else if (layer < 6)
+    hipLaunchKernelGGL((conv_kernel<32, 32, 0>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, 1.f);
+  else
+    hipLaunchKernelGGL((conv_kernel<32, 16, 1>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, out_scale);
+  return hipGetLastError();
+}
+
+// gradient w.r.t. the input of `layer` (layer >= 1), masked by the previous layer's ReLU
+hipError_t conv_bwd_data(int layer, const uint16_t *dz, const uint16_t *wtb, const uint16_t *act_prev, uint16_t *dx,
+                         int B, int N, hipStream_t s) {
+  const int npix = B * N * N;
+  const dim3 grid((npix + 255) / 256), blk(256);
+  if (layer == 6)
+    hipLaunchKernelGGL((conv_kernel<16, 32, 2>), grid, blk, 0, s, dz, wtb, nullptr, dx, act_prev, npix, N, 1.f);
+  else
+    hipLaunchKernelGGL((conv_kernel<32, 32, 2>), grid, blk, 0, s, dz, wtb, nullptr, dx, act_prev, npix, N, 1.f);
+  return hipGetLastError();
+}
+
+hipError_t wgrad(int layer, const uint16_t *x, const uint16_t *dz, float *dw, float *db, int B, int N, hipStream_t s) {
+  if (layer == 0)
+    hipLaunchKernelGGL((wgrad_kernel<8, 32>), dim3(B), dim3(256), 0, s, x, dz, dw, db, N);
+  else if (layer < 6)
+    hipLaunchKernelGGL((wgrad_kernel<32, 32>), dim3(B), dim3(256), 0, s, x, dz, dw, db, N);
+  else
+    hipLaunchKernelGGL((wgrad_kernel<32, 16>), dim3(B), dim3(256), 0, s, x, dz, dw, db, N);
+  return hipGetLastError();
+}
+
+hipError_t features(const float *slopes, const uint8_t *mask, uint16_t *feat, int B, int n, int N, float scale,
+                    hipStream_t s) {
+  const size_t total = (size_t)B * N * N;
+  hipLaunchKernelGGL(features_kernel, dim3((total + 255) / 256), dim3(256), 0, s, slopes, mask, feat, B, n, N, scale);
+  return hipGetLastError();
+}
+
+hipError_t loss_grad(const float *pred, const float *target, const uint8_t *mask, uint16_t *dz7, float *loss, int B,
+                     int n, int N, float scale, float inv_count, hipStream_t s) {
+  const size_t total = (size_t)B * N * N;
+  hipLaunchKernelGGL(loss_grad_kernel, dim3((total + 255) / 256), dim3(256), 0, s, pred, target, mask, dz7, loss, B,
+                     n, N, scale, inv_count);
+  return hipGetLastError();
+}
+
+hipError_t adam(float *w, const float *g, float *m1, float *m2, int count, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((count + 255) / 256), dim3(256), 0, s, w, g, m1, m2, count, lr, b1, b2, eps,
+                     c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t pack(const float *w, uint16_t *wt, uint16_t *wtb, int cin_s, int cout_s, int kpad_f, int kpad_b,
+                hipStream_t s) {
+  const int n = cout_s * kpad_f > cin_s * kpad_b ? cout_s * kpad_f : cin_s * kpad_b;
+  hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, wt, wtb, cin_s, cout_s, kpad_f, kpad_b);
+  return hipGetLastError();
+}
+
+}  // namespace cnn_launch
+}  // namespace fwr

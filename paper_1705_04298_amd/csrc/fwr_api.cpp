@@ -203,11 +203,14 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   return FWR_OK;
 }
 
-static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend) {
+static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
+                      const float *start = nullptr, float *resid = nullptr) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (in == nullptr || out == nullptr) return FWR_E_INVAL;
+  if ((start != nullptr || resid != nullptr) && plan->multipass) return FWR_E_UNSUPPORTED;
+  if (start != nullptr && plan->n_iter == 0) return FWR_E_INVAL;
   if (plan->multipass) {
     fwr::MPArgs a = plan->mp;
     a.slopes = in;
@@ -227,6 +230,8 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.o = plan->o;
   a.n_iter = plan->n_iter;
   a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
+  a.start = start;
+  a.resid = resid;
   return fwr::onchip_launch(plan->N, a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
@@ -236,6 +241,16 @@ fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int3
 
 fwr_status fwr_reconstruct(fwr_plan_t plan, const float *d_slopes, float *d_phase, int32_t B) {
   return run(plan, d_slopes, d_phase, B, false);
+}
+
+fwr_status fwr_extend_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_ext,
+                            float *d_resid, int32_t B) {
+  return run(plan, d_slopes, d_ext, B, true, d_start, d_resid);
+}
+
+fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_phase,
+                                 float *d_resid, int32_t B) {
+  return run(plan, d_slopes, d_phase, B, false, d_start, d_resid);
 }
 
 fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {

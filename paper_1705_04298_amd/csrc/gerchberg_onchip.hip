@@ -52,7 +52,8 @@ struct Onchip {
   // (n+1) * N complex) so that two workgroups share a CU; N = 128 keeps it in
   // registers (one workgroup per CU).
   static constexpr bool F0_IN_LDS = N <= 80;
-  static constexpr int STATIC_LDS_BYTES = (TILE + 2 * N + T * 4) * 8;
+  static constexpr int STATIC_LDS_BYTES =
+      (TILE + 2 * N + T * 4) * 8 + (THREADS % 64 == 0 ? 16 * (THREADS / 64) : 16 * THREADS);
   static int lds_bytes(int n) { return STATIC_LDS_BYTES + (F0_IN_LDS ? (n + 1) * PITCH * 8 : 0); }
   // Register budget: two workgroups per CU (80 KB of LDS each at N = 80) put
   // three waves on some SIMDs, i.e. at most 168 VGPRs.  The iteration loop fits
@@ -76,6 +77,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   constexpr int P = C::PITCH;
   __shared__ float2 buf[C::TILE];
   __shared__ float2 sums[2 * N];  // Eq. 5: column sums C_n, then row sums R_m
+  // residual partial sums: one set per wave (full waves) or per thread (N < 16)
+  constexpr bool FULL_WAVES = C::THREADS % 64 == 0;
+  __shared__ float red[FULL_WAVES ? 4 * (C::THREADS / 64) : 4 * C::THREADS];
   __shared__ float2 tw[T * 4];
   extern __shared__ float2 f0rows[];  // [(n+1)][PITCH], lane-blocked like the tile rows
 
@@ -140,6 +144,12 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   }
   const int f0row = (in_rows ? line - o : 0) * P + T * j;
   const float rowf = in_rows ? 1.f : 0.f;
+
+  const bool want_resid = a.resid != nullptr && a.n_iter > 0;
+  if (a.resid != nullptr && a.n_iter == 0 && t == 0) {
+    a.resid[fa] = 0.f;
+    if (hasB) a.resid[fa + 1] = 0.f;
+  }
 
   // neighbour column slots for n + 1 and n - 1 (lane-blocked layout)
   const int jp = (j + 1) & 3, jm = (j + 3) & 3;
@@ -240,6 +250,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     const size_t gplane = (size_t)N * N;
     float *ea = a.out + (size_t)fa * 2 * gplane;  // extended slopes of frame A (write mode)
     float2 rowacc = make_float2(0.f, 0.f), sx_last = make_float2(0.f, 0.f);
+    float ra = 0.f, rb = 0.f, na = 0.f, nb = 0.f;  // in-pupil misfit and measurement energy
     float2 DY[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
@@ -262,6 +273,14 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
       const float2 sxk = make_float2(select_bits(meas, mxa, gx.x), select_bits(meas, mxb, gx.y));
       const float2 syk = make_float2(select_bits(meas, mya, gy.x), select_bits(meas, myb, gy.y));
+      if (want_resid) {
+        const float mf = meas ? 1.f : 0.f;
+        const float ex = gx.x - mxa, ey = gy.x - mya, fx = gx.y - mxb, fy = gy.y - myb;
+        ra = fmaf(mf, ex * ex + ey * ey, ra);
+        rb = fmaf(mf, fx * fx + fy * fy, rb);
+        na = fmaf(mf, mxa * mxa + mya * mya, na);
+        nb = fmaf(mf, mxb * mxb + myb * myb, nb);
+      }
       rowacc = cadd(rowacc, sxk);
       DY[k] = syk;
       if (k == T - 1) sx_last = sxk;
@@ -294,6 +313,37 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         x[k] = r;
       }
       if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (want_resid) {  // block reduction of the four sums (fixed order), then one write per frame
+      constexpr int PARTS = FULL_WAVES ? C::THREADS / 64 : C::THREADS;
+      if constexpr (FULL_WAVES) {
+        for (int off = 32; off > 0; off >>= 1) {
+          ra += __shfl_xor(ra, off);
+          rb += __shfl_xor(rb, off);
+          na += __shfl_xor(na, off);
+          nb += __shfl_xor(nb, off);
+        }
+      }
+      __syncthreads();
+      if (!FULL_WAVES || (t & 63) == 0) {
+        const int slot = FULL_WAVES ? (t >> 6) : t;
+        red[4 * slot + 0] = ra;
+        red[4 * slot + 1] = rb;
+        red[4 * slot + 2] = na;
+        red[4 * slot + 3] = nb;
+      }
+      __syncthreads();
+      if (t == 0) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (int w = 0; w < PARTS; ++w) {
+          s0 += red[4 * w];
+          s1 += red[4 * w + 1];
+          s2 += red[4 * w + 2];
+          s3 += red[4 * w + 3];
+        }
+        a.resid[fa] = s2 > 0.f ? sqrtf(s0 / s2) : 0.f;
+        if (hasB) a.resid[fa + 1] = s3 > 0.f ? sqrtf(s1 / s3) : 0.f;
+      }
     }
     if (fix) {
       // R_m: quad reduction of the per-lane partial row sums
@@ -349,13 +399,49 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
 
   const bool periodic = (a.flags & kFlagPeriodic) != 0;
   const bool extend = (a.flags & kFlagExtend) != 0;
-  const bool need_final_step = periodic || extend || (EACH && a.n_iter > 0);
+  const bool need_final_step = periodic || extend || (EACH && a.n_iter > 0) || want_resid;
   const bool fix_final = periodic || (EACH && a.n_iter > 0);
 
   float2 x[T];
 #pragma unroll
   for (int k = 0; k < T; ++k) x[k] = f0[k];  // q2 of the zero-padded start
   __syncthreads();                           // tables and forcing in LDS
+  if (a.start != nullptr) {
+    // q2 of the given start: add the adjoint stencil of the start slopes on the
+    // out-of-pupil cells, -p(c1) + p(c2) + r(c3) - r(c4) (p = s_x + s_y, r = s_x - s_y),
+    // staging p then r through the tile in the own-slot layout
+    const size_t gplane = (size_t)N * N;
+    const float *st = a.start + (size_t)fa * 2 * gplane;
+    for (int pass = 0; pass < 2; ++pass) {
+      const float sg = pass == 0 ? 1.f : -1.f;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const size_t idx = (size_t)line * N + 4 * k + j;
+        const float ax = st[idx], ay = st[gplane + idx];
+        const float bx = hasB ? st[2 * gplane + idx] : 0.f, by = hasB ? st[3 * gplane + idx] : 0.f;
+        buf[line * P + T * j + k] = make_float2(fmaf(sg, ay, ax), fmaf(sg, by, bx));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const uint32_t c4 = code_of(k);
+        const float2 own = buf[line * P + T * j + k];  // cell (m, n)
+        const float2 ul = buf[up * P + slot_m(k)];     // cell (m-1, n-1)
+        const float2 lf = buf[line * P + slot_m(k)];   // cell (m, n-1)
+        const float2 upc = buf[up * P + T * j + k];    // cell (m-1, n)
+        float2 r = x[k];
+        if (pass == 0) {
+          r.x += (c4 & 1u ? -own.x : 0.f) + (c4 & 2u ? ul.x : 0.f);
+          r.y += (c4 & 1u ? -own.y : 0.f) + (c4 & 2u ? ul.y : 0.f);
+        } else {
+          r.x += (c4 & 4u ? lf.x : 0.f) - (c4 & 8u ? upc.x : 0.f);
+          r.y += (c4 & 4u ? lf.y : 0.f) - (c4 & 8u ? upc.y : 0.f);
+        }
+        x[k] = r;
+      }
+      __syncthreads();
+    }
+  }
 
   for (int it = 0; it < a.n_iter; ++it) {
     solve(x, a.h_loop);

@@ -18,6 +18,8 @@ struct OnchipArgs {
   const uint32_t *codes;  // [(T+7)/8][4N]: 4 bits per node of thread t, nodes 8w..8w+7 in word w;
                           // bit 0: cell (m, n) outside the pupil, bit 1: cell (m-1, n-1),
                           // bit 2: cell (m, n-1), bit 3: cell (m-1, n)
+  const float *start;     // optional [B][2][N][N]: out-of-pupil start slopes (NULL: zeros)
+  float *resid;           // optional [B]: in-pupil misfit of the last iteration
   int B, n, o, n_iter, flags;
 };
 

@@ -28,7 +28,10 @@ FWR_MODEL_FRIED = 0
 ONCHIP_GRIDS = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 128)
 
 EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set_stream",
-            "fwr_plan_launch_info", "fwr_status_string")
+            "fwr_plan_launch_info", "fwr_status_string", "fwr_extend_start", "fwr_reconstruct_start",
+            "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
+            "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy")
+CNN_PARAMS = 47714
 
 
 class FwrParams(ctypes.Structure):
@@ -84,6 +87,26 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_plan_launch_info.restype = ctypes.c_int
     lib.fwr_status_string.argtypes = [ctypes.c_int32]
     lib.fwr_status_string.restype = ctypes.c_char_p
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    for name in ("fwr_extend_start", "fwr_reconstruct_start"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp, vp, i32]
+        f.restype = ctypes.c_int
+    lib.fwr_cnn_create.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_uint8), i32, f32, i32, vp,
+                                   ctypes.POINTER(vp)]
+    lib.fwr_cnn_create.restype = ctypes.c_int
+    for name in ("fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_get_grads"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+        f.restype = ctypes.c_int
+    lib.fwr_cnn_forward.argtypes = [vp, vp, vp, i32]
+    lib.fwr_cnn_forward.restype = ctypes.c_int
+    lib.fwr_cnn_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
+    lib.fwr_cnn_backward.restype = ctypes.c_int
+    lib.fwr_cnn_adam_step.argtypes = [vp, f32]
+    lib.fwr_cnn_adam_step.restype = ctypes.c_int
+    lib.fwr_cnn_destroy.argtypes = [vp]
+    lib.fwr_cnn_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -108,6 +131,15 @@ def fwr_extend(plan, d_slopes: int, d_ext: int, B: int) -> int:
 
 def fwr_reconstruct(plan, d_slopes: int, d_phase: int, B: int) -> int:
     return load().fwr_reconstruct(plan, ctypes.c_void_p(d_slopes), ctypes.c_void_p(d_phase), int(B))
+
+
+def fwr_extend_start(plan, d_slopes: int, d_start: int, d_ext: int, d_resid: int, B: int) -> int:
+    return load().fwr_extend_start(plan, d_slopes or None, d_start or None, d_ext or None, d_resid or None, int(B))
+
+
+def fwr_reconstruct_start(plan, d_slopes: int, d_start: int, d_phase: int, d_resid: int, B: int) -> int:
+    return load().fwr_reconstruct_start(plan, d_slopes or None, d_start or None, d_phase or None,
+                                        d_resid or None, int(B))
 
 
 def fwr_destroy(plan) -> int:
@@ -171,26 +203,46 @@ class Plan:
         if tuple(t.shape) != tuple(shape):
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
-    def reconstruct(self, slopes, out=None):
+    def _start_args(self, start, resid, B):
+        sp = rp = 0
+        if start is not None:
+            self._check(start, (B, 2, self.n_grid, self.n_grid), "start")
+            sp = start.data_ptr()
+        if resid is not None:
+            self._check(resid, (B,), "resid")
+            rp = resid.data_ptr()
+        return sp, rp
+
+    def reconstruct(self, slopes, out=None, start=None, resid=None):
+        """Phase [B, n+1, n+1]; optional start slopes [B, 2, N, N] and residual output [B]."""
         import torch
         B = slopes.shape[0]
         self._check(slopes, (B, 2, self.n_sub, self.n_sub), "slopes")
         if out is None:
             out = torch.empty((B, self.n_sub + 1, self.n_sub + 1), device=slopes.device, dtype=torch.float32)
         self._check(out, (B, self.n_sub + 1, self.n_sub + 1), "out")
-        st = fwr_reconstruct(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        if start is None and resid is None:
+            st = fwr_reconstruct(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        else:
+            sp, rp = self._start_args(start, resid, B)
+            st = fwr_reconstruct_start(self._h, slopes.data_ptr(), sp, out.data_ptr(), rp, B)
         if st != FWR_OK:
             raise FwrError(st, "fwr_reconstruct")
         return out
 
-    def extend(self, slopes, out=None):
+    def extend(self, slopes, out=None, start=None, resid=None):
+        """Extended slopes [B, 2, N, N]; optional start slopes and residual output as reconstruct."""
         import torch
         B = slopes.shape[0]
         self._check(slopes, (B, 2, self.n_sub, self.n_sub), "slopes")
         if out is None:
             out = torch.empty((B, 2, self.n_grid, self.n_grid), device=slopes.device, dtype=torch.float32)
         self._check(out, (B, 2, self.n_grid, self.n_grid), "out")
-        st = fwr_extend(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        if start is None and resid is None:
+            st = fwr_extend(self._h, slopes.data_ptr(), out.data_ptr(), B)
+        else:
+            sp, rp = self._start_args(start, resid, B)
+            st = fwr_extend_start(self._h, slopes.data_ptr(), sp, out.data_ptr(), rp, B)
         if st != FWR_OK:
             raise FwrError(st, "fwr_extend")
         return out
@@ -208,3 +260,91 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class CNN:
+    """Learned initial extension (fwr_cnn_* calls).  Parameters are a flat float32 array of
+    47714 values: per layer, weights [out][in][3][3] then biases [out]."""
+
+    def __init__(self, n_sub: int, n_grid: int, mask, max_batch: int, input_scale: float = 0.5,
+                 training: bool = False, stream: Optional[int] = None):
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        self.n_sub, self.n_grid, self.max_batch = int(n_sub), int(n_grid), int(max_batch)
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = ctypes.c_void_p()
+        st = load().fwr_cnn_create(self.n_sub, self.n_grid, mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   self.max_batch, float(input_scale), int(bool(training)), self.stream,
+                                   ctypes.byref(h))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_create")
+        self._h = h
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        st = load().fwr_cnn_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_set_params")
+
+    def _get(self, fn, what):
+        a = np.empty(CNN_PARAMS, dtype=np.float32)
+        st = fn(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size)
+        if st != FWR_OK:
+            raise FwrError(st, what)
+        return a
+
+    def get_params(self) -> np.ndarray:
+        return self._get(load().fwr_cnn_get_params, "fwr_cnn_get_params")
+
+    def get_grads(self) -> np.ndarray:
+        return self._get(load().fwr_cnn_get_grads, "fwr_cnn_get_grads")
+
+    def forward(self, slopes, pred=None):
+        import torch
+        B = slopes.shape[0]
+        if pred is None:
+            pred = torch.empty((B, 2, self.n_grid, self.n_grid), device=slopes.device, dtype=torch.float32)
+        st = load().fwr_cnn_forward(self._h, slopes.data_ptr(), pred.data_ptr(), B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_forward")
+        return pred
+
+    def backward(self, pred, target) -> float:
+        loss = ctypes.c_float()
+        st = load().fwr_cnn_backward(self._h, pred.data_ptr(), target.data_ptr(), pred.shape[0],
+                                     ctypes.byref(loss))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_backward")
+        return float(loss.value)
+
+    def adam_step(self, lr: float):
+        st = load().fwr_cnn_adam_step(self._h, float(lr))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fwr_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params_to_flat(params) -> np.ndarray:
+    """[(w [O][C][3][3], b [O]), ...] -> flat float32 array in the library's layout."""
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def flat_to_params(flat: np.ndarray, layers):
+    out, i = [], 0
+    for cin, cout in layers:
+        nw = cout * cin * 9
+        w = flat[i:i + nw].reshape(cout, cin, 3, 3)
+        i += nw
+        b = flat[i:i + cout]
+        i += cout
+        out.append((w.astype(np.float64), b.astype(np.float64)))
+    return out

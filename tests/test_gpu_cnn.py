@@ -1,0 +1,147 @@
+"""Learned initial extension on the GPU vs the FP64 oracles (needs an MI355X).
+
+BF16 weights/activations with FP32 accumulation: the network output and the
+gradients are compared at a relative L2 tolerance of a few 1e-2; the start-value
+variants of Algorithm 1 keep the 1e-5 phase tolerance of the plain path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn as C
+from oracle import fwr_oracle as O
+from paper_1705_04298_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SCALE = 0.5
+SPHERE = dict(n_sub=40, n_grid=80, d=0.2, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_04298_amd import fwr
+    fwr.load()
+    return fwr
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _oracle_inputs(slopes, mask, N):
+    grid = np.stack([np.stack(O.padded_measurement(s, mask, N)[:2]) for s in slopes])
+    P = O.pupil_on_grid(mask, N)
+    return C.features(grid, P, SCALE), P
+
+
+def test_cnn_forward_matches_oracle(F):
+    _flush("[gpu] cnn forward")
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 2, start=200, dtype=np.float32).astype(np.float64)
+    params = C.init_params(7)
+    params = [(w, np.random.default_rng(l).standard_normal(b.shape) * 0.05) for l, (w, b) in enumerate(params)]
+    net = F.CNN(40, 80, mask, max_batch=2, input_scale=SCALE, training=False)
+    net.set_params(F.params_to_flat(params))
+    x = torch.from_numpy(slopes.astype(np.float32)).cuda()
+    pred = net.forward(x)
+    torch.cuda.synchronize()
+    got = pred.cpu().numpy().astype(np.float64)
+    feats, _ = _oracle_inputs(slopes, mask, 80)
+    want = C.forward(feats, params)[-1] / SCALE
+    assert rel(got, want) < 3e-2, rel(got, want)
+    back = net.get_params()
+    assert np.array_equal(back, F.params_to_flat(params))
+    net.close()
+
+
+def test_cnn_gradients_match_oracle(F):
+    _flush("[gpu] cnn gradients")
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 2, start=210, dtype=np.float32).astype(np.float64)
+    target = np.random.default_rng(3).standard_normal((2, 2, 80, 80))
+    params = C.init_params(11)
+    params = [(w, np.random.default_rng(10 + l).standard_normal(b.shape) * 0.05) for l, (w, b) in enumerate(params)]
+    net = F.CNN(40, 80, mask, max_batch=2, input_scale=SCALE, training=True)
+    net.set_params(F.params_to_flat(params))
+    x = torch.from_numpy(slopes.astype(np.float32)).cuda()
+    tgt = torch.from_numpy(target.astype(np.float32)).cuda()
+    pred = net.forward(x)
+    loss = net.backward(pred, tgt)
+    grads = F.flat_to_params(net.get_grads(), C.LAYERS)
+    feats, P = _oracle_inputs(slopes, mask, 80)
+    acts = C.forward(feats, params)
+    want_loss, g = C.masked_mse(acts[-1], target * SCALE, ~P)
+    want = C.backward(acts, params, g)
+    assert abs(loss - want_loss) / want_loss < 2e-2
+    for li, ((gw, gb), (ww, wb)) in enumerate(zip(grads, want)):
+        assert rel(gw, ww) < 5e-2, (li, rel(gw, ww))
+        assert rel(gb, wb) < 5e-2, (li, rel(gb, wb))
+    net.close()
+
+
+def test_adam_steps_reduce_the_loss(F):
+    _flush("[gpu] cnn adam")
+    mask = I.pupil_mask(40)
+    slopes = torch.from_numpy(I.make_batch(I.SPHERE_40, 8, start=220, dtype=np.float32)).cuda()
+    plan = F.Plan(40, 80, mask, n_iter=30, periodic=False, max_batch=8)
+    target = plan.extend(slopes)
+    net = F.CNN(40, 80, mask, max_batch=8, input_scale=SCALE, training=True)
+    net.set_params(F.params_to_flat(C.init_params(1)))
+    losses = []
+    for _ in range(30):
+        pred = net.forward(slopes)
+        losses.append(net.backward(pred, target))
+        net.adam_step(1e-3)
+    assert losses[-1] < 0.7 * losses[0], losses
+    net.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_start_values_match_oracle(F, periodic):
+    _flush(f"[gpu] start values periodic={periodic}")
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 3, start=230, dtype=np.float32)
+    start = (np.random.default_rng(4).standard_normal((3, 2, 80, 80)) * 2.0).astype(np.float32)
+    p = O.Params(n_iter=3, periodic=periodic, **SPHERE)
+    plan = F.Plan(40, 80, mask, n_iter=3, periodic=periodic, max_batch=3)
+    x = torch.from_numpy(slopes).cuda()
+    st = torch.from_numpy(start).cuda()
+    resid = torch.empty(3, device="cuda")
+    ext = plan.extend(x, start=st, resid=resid).cpu().numpy().astype(np.float64)
+    phase = plan.reconstruct(x, start=st).cpu().numpy().astype(np.float64)
+    r = resid.cpu().numpy()
+    for b in range(3):
+        s64 = slopes[b].astype(np.float64)
+        ref = O.extend(s64, mask, p, start=(start[b, 0].astype(np.float64), start[b, 1].astype(np.float64)))
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(ext[b, 0] - ref.sx).max() <= 1e-4 * scale
+        assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
+        assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
+        want = O.reconstruct(s64, mask, p, start=(start[b, 0].astype(np.float64), start[b, 1].astype(np.float64)))
+        assert rel(phase[b], want) <= 1e-5
+    plan.close()
+
+
+def test_residual_of_the_plain_loop(F):
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 4, start=240, dtype=np.float32)
+    for n_iter in (1, 10):
+        plan = F.Plan(40, 80, mask, n_iter=n_iter, periodic=False, max_batch=4)
+        resid = torch.empty(4, device="cuda")
+        plan.reconstruct(torch.from_numpy(slopes).cuda(), resid=resid)
+        r = resid.cpu().numpy()
+        for b in range(4):
+            ref = O.extend(slopes[b].astype(np.float64), mask, O.Params(n_iter=n_iter, periodic=False, **SPHERE))
+            assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
+        plan.close()
