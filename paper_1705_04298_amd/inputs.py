@@ -171,3 +171,48 @@ def random_slopes(B: int, n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """White ``float64[B, 2, n, n]`` slopes for small-grid tests (not turbulence-like)."""
     rng = np.random.default_rng([SEED_BASE, 98, seed])
     return rng.standard_normal((B, 2, n, n)) * scale
+
+
+# ---------------------------------------------------------------------------
+# Training frames for the learned initial extension
+# ---------------------------------------------------------------------------
+
+LEARNED_SCREEN = 1024   # one screen gives (1024 // 41)^2 = 576 disjoint 41x41 node windows
+LEARNED_CONFIG = 4
+
+
+def training_frames(count: int, n: int = 40, diameter: float = 8.0, seed: int = 0,
+                    r0_range=(0.08, 0.20), sigma_range=(0.0, 0.1), L0: float = 25.0):
+    """``count`` frames with per-frame r0 ~ U(r0_range) and noise sigma ~ U(sigma_range).
+
+    Phases are disjoint (n+1) x (n+1) windows of large periodic von Karman screens
+    drawn at r0 = 0.15 m and rescaled by (0.15 / r0)^(5/6) (the PSD scales as
+    r0^(-5/3)).  Returns ``(slopes float32[count, 2, n, n], phase float32[count, n+1, n+1],
+    r0 float64[count], sigma float64[count])``; slopes are zero on invalid subapertures.
+    """
+    d = diameter / n
+    per = (LEARNED_SCREEN // (n + 1)) ** 2
+    m = pupil_mask(n).astype(bool)
+    slopes = np.zeros((count, 2, n, n), dtype=np.float32)
+    phase = np.zeros((count, n + 1, n + 1), dtype=np.float32)
+    rng = np.random.default_rng([SEED_BASE, LEARNED_CONFIG, seed])
+    r0 = rng.uniform(*r0_range, count)
+    sig = rng.uniform(*sigma_range, count)
+    side = LEARNED_SCREEN // (n + 1)
+    i = 0
+    s = 0
+    while i < count:
+        scr = vk_screen(frame_rng(LEARNED_CONFIG, 1_000_000 * (seed + 1) + s), LEARNED_SCREEN, d, 0.15, L0)
+        s += 1
+        for w in range(per):
+            if i >= count:
+                break
+            a, b = divmod(w, side)
+            phi = scr[a * (n + 1):(a + 1) * (n + 1), b * (n + 1):(b + 1) * (n + 1)] * (0.15 / r0[i]) ** (5.0 / 6.0)
+            sx, sy = fried_slopes_from_nodes(phi)
+            noise = rng.standard_normal((2, n, n)) * sig[i]
+            slopes[i, 0] = np.where(m, sx + noise[0], 0.0)
+            slopes[i, 1] = np.where(m, sy + noise[1], 0.0)
+            phase[i] = phi
+            i += 1
+    return slopes, phase, r0, sig

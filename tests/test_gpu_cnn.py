@@ -145,3 +145,44 @@ def test_residual_of_the_plain_loop(F):
             ref = O.extend(slopes[b].astype(np.float64), mask, O.Params(n_iter=n_iter, periodic=False, **SPHERE))
             assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
         plan.close()
+
+
+def test_trained_network_gains_over_zero_start(F):
+    """The trained network (weights shipped with the package) starts Algorithm 1 closer to the
+    converged extension: on held-out frames CNN + 2 iterations has a lower in-pupil residual than
+    2 plain iterations, and CNN + 10 a lower error vs the true phase than 10 plain iterations."""
+    import os
+    from paper_1705_04298_amd import learned as L
+    path = os.path.join(os.path.dirname(L.__file__), "weights", "cnn_40x40_fried.npz")
+    params = np.load(path)["params"]
+    slopes, truth = L.make_frames(512, seed0=77_000)
+    x = torch.from_numpy(slopes).cuda()
+    mask = I.pupil_mask(40)
+    nodes = L._pupil_nodes()
+    net = F.CNN(40, 80, mask, max_batch=512, input_scale=L.INPUT_SCALE)
+    net.set_params(params)
+    start = net.forward(x)
+    out = {}
+    for k in (2, 10):
+        plan = F.Plan(40, 80, mask, n_iter=k, periodic=True, max_batch=512)
+        for label, st in (("plain", None), ("cnn", start)):
+            resid = torch.empty(512, device="cuda")
+            ph = plan.reconstruct(x, start=st, resid=resid).cpu().numpy()
+            e = (ph - truth)[:, nodes]
+            e = e - e.mean(axis=1, keepdims=True)
+            out[(label, k)] = (float(np.median(resid.cpu().numpy())), float(np.median(np.sqrt((e * e).mean(1)))))
+        plan.close()
+    assert out[("cnn", 2)][0] < 0.75 * out[("plain", 2)][0], out
+    assert out[("cnn", 10)][1] < out[("plain", 10)][1], out
+    # fallback: threshold 0 recomputes every frame with the plain loop (bit-identical to it)
+    lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=0.0, max_batch=512)
+    ph, resid, bad = lr.reconstruct(x)
+    plain = F.Plan(40, 80, mask, n_iter=10, periodic=True, max_batch=512)
+    assert bool(bad.all()) and torch.equal(ph, plain.reconstruct(x))
+    lr.close()
+    lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=1e9, max_batch=512)
+    ph, resid, bad = lr.reconstruct(x)
+    assert not bool(bad.any())
+    lr.close()
+    plain.close()
+    net.close()
