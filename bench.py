@@ -115,12 +115,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cnn", action="store_true", help="uneven workload: plain start for the 40x40 frames")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = up to 16; use 1 under a profiler)")
-    ap.add_argument("--workload", choices=("sphere40", "elt128"), default="sphere40",
+    ap.add_argument("--workload", choices=("sphere40", "elt128", "uneven"), default="sphere40",
                     help="sphere40: the headline 4096 x 40x40 batch; elt128: 128 x 128x128 frames on "
-                         "the 256x256 multi-pass path (prints its own line)")
+                         "the 256x256 multi-pass path; uneven: the mixed-size closed loop captured in a "
+                         "HIP graph (each prints its own line)")
+    ap.add_argument("--graph-steps", type=int, default=1000,
+                    help="uneven workload: timed graph replays (one loop step each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -135,6 +139,8 @@ def main():
         return
     if args.workload == "elt128":
         return elt_main(args)
+    if args.workload == "uneven":
+        return uneven_main(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (frames are independent; see the design notes "
               f"for how the batch shards): --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -251,6 +257,106 @@ def elt_main(args):
                       "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": 8000.0,
                                    "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / 8e12, "traffic": None}}),
           flush=True)
+
+
+UNEVEN = ((24, 2048, 8.0 / 24), (40, 2048, 8.0 / 40), (64, 512, 8.0 / 64), (128, 64, 39.0 / 128))
+
+
+def uneven_main(args):
+    """Mixed closed loop: 2048 x 24x24, 2048 x 40x40 (learned start), 512 x 64x64, 64 x 128x128 frames,
+    each padded 2x, 10 iterations + Eq. 5 + MMSE.  One loop step = fresh frames from the device
+    generator (the next frames of each seeded sequence) + the network's start for the 40x40 frames +
+    one grouped reconstruction; the step is captured once in a HIP graph and replayed.  Reports
+    frames/s over the replays and the per-step latency percentiles (HIP events around each replay)."""
+    import torch
+    from paper_1705_04298_amd import fwr
+    from paper_1705_04298_amd import learned as L
+    torch.cuda.set_device(0)
+    seed = 0x5EED_0517_0504_298
+    plans, xs, outs, ctrs, starts = [], [], [], [], []
+    net = None
+    for n, B, d in UNEVEN:
+        plan = fwr.Plan(n, 2 * n, I.pupil_mask(n), n_iter=N_ITER, periodic=True, gamma=1.0,
+                        noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=d, max_batch=B)
+        plans.append(plan)
+        xs.append(torch.empty((B, 2, n, n), device="cuda"))
+        outs.append(torch.empty((B, n + 1, n + 1), device="cuda"))
+        ctrs.append(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        starts.append(None)
+        if n == L.N_SUB and not args.no_cnn:
+            net = fwr.CNN(n, 2 * n, I.pupil_mask(n), max_batch=B, input_scale=L.INPUT_SCALE)
+            net.set_params(np.load(os.path.join(ROOT, "paper_1705_04298_amd", "weights",
+                                                "cnn_40x40_fried.npz"))["params"])
+            starts[-1] = torch.empty((B, 2, 2 * n, 2 * n), device="cuda")
+    work = [(p, x, o, s, None) for p, x, o, s in zip(plans, xs, outs, starts)]
+
+    def step():
+        for p, x, c in zip(plans, xs, ctrs):
+            p.generate(x.shape[0], seed, counter=c, slopes=x, r0=0.15, L0=25.0, sigma=0.05)
+        for x, s in zip(xs, starts):
+            if s is not None:
+                net.forward(x, s)
+        fwr.reconstruct_group(work)
+
+    def rebind():
+        for p in plans:
+            p.set_stream()
+        if net is not None:
+            net.set_stream()
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rebind()
+        for _ in range(2):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    # eager steps (one stream, launches from Python) for comparison
+    rebind()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / 20
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rebind()
+        step()
+    rebind()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    K = args.graph_steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    ev[0].record()
+    for k in range(K):
+        g.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
+    total_ms = ev[0].elapsed_time(ev[K])
+    frames = sum(B for _, B, _ in UNEVEN)
+    line = {
+        "metric": "frames/s, uneven mixed-size closed loop (10 Gerchberg iters, graph-captured steps)",
+        "value": frames * K / (total_ms / 1e3), "unit": "frames/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": total_ms / K, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic (device generator, fresh frames every step)",
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max()), "mean": float(lat.mean())},
+        "eager_ms_per_step": eager_ms,
+        "config": {"workload": "2048x24^2 + 2048x40^2 (CNN start) + 512x64^2 + 64x128^2 SH frames, padded 2x, "
+                               "10 iterations + Eq.5 + MMSE, fresh von Karman frames each step",
+                   "items": [{"n_sub": n, "frames": B} for n, B, _ in UNEVEN],
+                   "learned_start": net is not None},
+    }
+    for p in plans:
+        p.close()
+    if net is not None:
+        net.close()
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -133,6 +133,51 @@ fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const f
                                  float *d_resid, int32_t B);
 
 /* ------------------------------------------------------------------------
+ * Mixed batches and synthetic frames.
+ *
+ * fwr_reconstruct_group: several plans (grid sizes, iteration counts) with their
+ * batches in one call.  The items run concurrently on library-owned streams
+ * that fork from and join back into `stream` (hipStream_t; captured as parallel
+ * branches when `stream` is being captured into a HIP graph).  Each item is as
+ * fwr_reconstruct (d_start / d_resid optional, as fwr_reconstruct_start).  A
+ * plan may appear in one item only (its workspace serves one batch at a time);
+ * one call at a time per process.
+ */
+typedef struct {
+  fwr_plan_t plan;
+  const float *d_slopes;    /* [B][2][n][n] */
+  float *d_phase;           /* [B][n+1][n+1] */
+  const float *d_start;     /* optional [B][2][N][N] start slopes, NULL = zeros */
+  float *d_resid;           /* optional [B] residual */
+  int32_t B;
+} fwr_work;
+fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *stream);
+
+/* fwr_generate: synthetic frames on the device for the plan's geometry, a
+ * stand-in for measured data: a periodic von Karman phase screen on the padded
+ * N x N grid (pitch = the plan's d, Fried parameter r0 and outer scale L0 [m],
+ * phase in radians at the r0 wavelength), its Fried slopes on the lenslet
+ * window (grid cells [o, o+n)), white Gaussian noise of `noise_sigma` [rad],
+ * zeros on invalid subapertures.  Frame i of the batch is frame
+ * first_frame + i (+ *d_counter when d_counter != NULL) of the sequence keyed
+ * by `seed` (Philox4x32-10 counters, so a frame does not depend on its batch);
+ * first_frame must be even.  When d_counter (DEVICE uint64) is given it is
+ * advanced by the batch size afterwards, so a graph replay draws fresh frames.
+ * d_slopes: float[B][2][n][n]; d_phase (optional): float[B][n+1][n+1] true node phase.
+ * Random numbers, for frame pair p (frames 2p, 2p+1) and key (seed low, seed high word):
+ *   spectral sample (l, k), l, k in [0, N): Philox counter (p low, p high, l N + k, 0),
+ *     words 0, 1 -> Box-Muller -> (g0, g1); screen pair = sum of (g0 + i g1) a(l, k)
+ *     e^{+2 pi i (l m + k n) / N}, a = sqrt(Phi_vK(kappa)) / (N d), a(0, 0) = 0; the real
+ *     part is frame 2p, the imaginary part frame 2p+1;
+ *   noise of subaperture idx = i n + j: counter (p low, p high, idx, 1), words 0, 1 -> x, y
+ *     noise of frame 2p, words 2, 3 -> x, y noise of frame 2p+1;
+ *   Box-Muller on words (a, b): u1 = ((a >> 8) + 1) / 2^24, u2 = (b >> 8) / 2^24,
+ *     (r cos 2 pi u2, r sin 2 pi u2), r = sqrt(-2 ln u1).
+ * Uses the plan's stream (and, for N = 256, its workspace). */
+fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, uint64_t *d_counter, float r0,
+                        float L0, float noise_sigma, float *d_slopes, float *d_phase, int32_t B);
+
+/* ------------------------------------------------------------------------
  * Learned initial extension (not part of the paper's method).
  *
  * A seven-layer 3x3 CNN (channels 3-32-32-32-32-32-32-2, ReLU after all but
@@ -165,6 +210,8 @@ fwr_status fwr_cnn_backward(fwr_cnn_t cnn, const float *d_pred, const float *d_t
 fwr_status fwr_cnn_get_grads(fwr_cnn_t cnn, float *h_grads, int32_t count);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
 fwr_status fwr_cnn_adam_step(fwr_cnn_t cnn, float lr);
+/* Rebind the network to another stream (hipStream_t), e.g. a stream being captured. */
+fwr_status fwr_cnn_set_stream(fwr_cnn_t cnn, void *stream);
 fwr_status fwr_cnn_destroy(fwr_cnn_t cnn);
 
 /* Static description of a status code (never NULL). */

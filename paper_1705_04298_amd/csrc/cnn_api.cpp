@@ -269,6 +269,12 @@ fwr_status fwr_cnn_adam_step(fwr_cnn_t c, float lr) {
   return repack(c);
 }
 
+fwr_status fwr_cnn_set_stream(fwr_cnn_t c, void *stream) {
+  if (!valid(c)) return FWR_E_STATE;
+  c->stream = static_cast<hipStream_t>(stream);
+  return FWR_OK;
+}
+
 fwr_status fwr_cnn_destroy(fwr_cnn_t c) {
   if (!valid(c)) return FWR_E_STATE;
   (void)hipStreamSynchronize(c->stream);

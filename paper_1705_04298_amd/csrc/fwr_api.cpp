@@ -9,6 +9,9 @@
 #include <vector>
 
 #include "../../include/fwr.h"
+#include <mutex>
+
+#include "gen.h"
 #include "multipass.h"
 #include "onchip.h"
 
@@ -39,6 +42,8 @@ struct fwr_plan_s {
   // multi-pass path (N = 256)
   bool multipass = false;
   fwr::MPArgs mp{};
+  const uint8_t *dmask = nullptr;  // [n][n] valid subapertures on the device (generator)
+  double d = 0.0;                  // lenslet pitch [m]
 };
 
 namespace {
@@ -170,7 +175,10 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const size_t b_h = h_loop.size() * sizeof(float);
   const size_t b_tw = tw.size() * sizeof(float2);
   const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
-  const size_t total = off_codes + codes.size() * sizeof(uint32_t);
+  const size_t off_dmask = off_codes + codes.size() * sizeof(uint32_t);
+  const size_t total = off_dmask + (size_t)n * n;
+  std::vector<uint8_t> dmask((size_t)n * n);
+  for (size_t i = 0; i < dmask.size(); ++i) dmask[i] = p.mask[i] ? 1 : 0;
   char *mem = nullptr;
   if (hipMalloc(reinterpret_cast<void **>(&mem), total) != hipSuccess) {
     delete plan;
@@ -181,6 +189,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(mem + off_codes, codes.data(), codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_dmask, dmask.data(), dmask.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(mem);
     delete plan;
@@ -199,12 +208,16 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   plan->h_final = reinterpret_cast<const float *>(mem + off_hf);
   plan->tw_lane = reinterpret_cast<const float2 *>(mem + off_tw);
   plan->codes = reinterpret_cast<const uint32_t *>(mem + off_codes);
+  plan->dmask = reinterpret_cast<const uint8_t *>(mem + off_dmask);
+  plan->d = p.d;
   *out = plan;
   return FWR_OK;
 }
 
 static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
-                      const float *start = nullptr, float *resid = nullptr) {
+                      const float *start = nullptr, float *resid = nullptr, hipStream_t stream = nullptr,
+                      bool use_stream = false) {
+  const hipStream_t st = use_stream ? stream : (valid(plan) ? plan->stream : nullptr);
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
@@ -216,7 +229,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.slopes = in;
     a.out = out;
     a.B = B;
-    return fwr::multipass_run(a, extend, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+    return fwr::multipass_run(a, extend, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
   fwr::OnchipArgs a;
   a.slopes = in;
@@ -232,7 +245,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
   a.start = start;
   a.resid = resid;
-  return fwr::onchip_launch(plan->N, a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  return fwr::onchip_launch(plan->N, a, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
 fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
@@ -251,6 +264,76 @@ fwr_status fwr_extend_start(fwr_plan_t plan, const float *d_slopes, const float 
 fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_phase,
                                  float *d_resid, int32_t B) {
   return run(plan, d_slopes, d_phase, B, false, d_start, d_resid);
+}
+
+fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *stream) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> pool;
+  static std::vector<hipEvent_t> evs;
+  if (n_work < 0 || (n_work > 0 && work == nullptr)) return FWR_E_INVAL;
+  for (int i = 0; i < n_work; ++i) {
+    if (!valid(work[i].plan)) return FWR_E_STATE;
+    for (int k = 0; k < i; ++k)
+      if (work[k].plan == work[i].plan) return FWR_E_INVAL;  // a plan's workspace serves one item
+  }
+  if (n_work == 0) return FWR_OK;
+  std::lock_guard<std::mutex> lock(mu);
+  while ((int)pool.size() < n_work) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return FWR_E_DEVICE;
+    pool.push_back(s);
+  }
+  while ((int)evs.size() < n_work + 1) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FWR_E_DEVICE;
+    evs.push_back(e);
+  }
+  const hipStream_t main = static_cast<hipStream_t>(stream);
+  if (hipEventRecord(evs[n_work], main) != hipSuccess) return FWR_E_DEVICE;
+  fwr_status status = FWR_OK;
+  for (int i = 0; i < n_work; ++i) {
+    if (hipStreamWaitEvent(pool[i], evs[n_work], 0) != hipSuccess) return FWR_E_DEVICE;
+    const fwr_work &w = work[i];
+    const fwr_status st = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, pool[i], true);
+    if (st != FWR_OK && status == FWR_OK) status = st;
+    if (hipEventRecord(evs[i], pool[i]) != hipSuccess) return FWR_E_DEVICE;
+    if (hipStreamWaitEvent(main, evs[i], 0) != hipSuccess) return FWR_E_DEVICE;
+  }
+  return status;
+}
+
+fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, uint64_t *d_counter, float r0,
+                        float L0, float noise_sigma, float *d_slopes, float *d_phase, int32_t B) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (B < 0 || B > plan->max_batch || (first_frame & 1u)) return FWR_E_INVAL;
+  if (B == 0) return FWR_OK;
+  if (d_slopes == nullptr || !(r0 > 0.f) || !(L0 > 0.f) || !(noise_sigma >= 0.f) || !(plan->d > 0.0))
+    return FWR_E_INVAL;
+  fwr::GenArgs g{};
+  g.slopes = d_slopes;
+  g.phase = d_phase;
+  g.mask = plan->dmask;
+  g.d_counter = d_counter;
+  g.first_pair = first_frame / 2;
+  g.seed_lo = uint32_t(seed);
+  g.seed_hi = uint32_t(seed >> 32);
+  g.r0 = r0;
+  g.L0 = L0;
+  g.d = float(plan->d);
+  g.sigma = noise_sigma;
+  g.vk_const = float(vk_constant());
+  g.B = B;
+  g.n = plan->n;
+  g.o = plan->o;
+  hipError_t e;
+  if (plan->multipass) {
+    fwr::MPArgs a = plan->mp;
+    a.B = B;
+    e = fwr::multipass_generate(a, g, plan->stream);
+  } else {
+    e = fwr::gen_launch(plan->N, g, plan->stream);
+  }
+  return e == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
 fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
@@ -371,6 +454,8 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   plan->stream = static_cast<hipStream_t>(p.stream);
   plan->d_mem = mem;
   plan->multipass = true;
+  plan->dmask = a.mask;
+  plan->d = p.d;
   *out = plan;
   return FWR_OK;
 }

@@ -374,3 +374,143 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
 }
 
 }  // namespace fwr
+
+// ---------------------------------------------------------------- device frames, N = 256
+#include "gen.h"
+
+namespace fwr {
+namespace mp {
+
+__device__ __forceinline__ uint64_t philox_pair(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1, uint32_t *out4) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n1 = uint32_t(p1);
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1, n3 = uint32_t(p0);
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out4[0] = c0;
+  out4[1] = c1;
+  out4[2] = c2;
+  out4[3] = c3;
+  return 0;
+}
+
+__device__ __forceinline__ float2 bm(uint32_t a, uint32_t b) {
+  const float u1 = (float(a >> 8) + 1.0f) * (1.0f / 16777216.0f);
+  const float u2 = float(b >> 8) * (1.0f / 16777216.0f);
+  const float r = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  return make_float2(r * c, r * s);
+}
+
+// spectrum in digit-reversed positions (row position q, column position c)
+__global__ __launch_bounds__(THREADS) void gen_spectrum_kernel(MPArgs a, GenArgs g) {
+  const int pair = blockIdx.y;
+  const uint64_t gp = g.first_pair + pair + (g.d_counter ? *g.d_counter / 2 : 0);
+  float2 *S = a.spec + field(pair);
+  const float dk = 1.0f / (float(NN) * g.d);
+  for (int i = threadIdx.x; i < R * NN; i += THREADS) {
+    const int q = blockIdx.x * R + i / NN, c = i % NN;
+    const int l = (q >> 4) + 16 * (q & 15), k = (c >> 4) + 16 * (c & 15);
+    float amp = 0.f;
+    if (l != 0 || k != 0) {
+      const int ks = k < NN / 2 ? k : k - NN, ls = l < NN / 2 ? l : l - NN;
+      const float kap2 = (float(ks) * ks + float(ls) * ls) * dk * dk;
+      const float psd = g.vk_const * powf(g.r0, -5.0f / 3.0f) * powf(kap2 + 1.0f / (g.L0 * g.L0), -11.0f / 6.0f);
+      amp = sqrtf(psd) * dk;
+    }
+    uint32_t r4[4];
+    philox_pair(uint32_t(gp), uint32_t(gp >> 32), uint32_t(l * NN + k), 0u, g.seed_lo, g.seed_hi, r4);
+    const float2 z = bm(r4[0], r4[1]);
+    S[(size_t)q * NN + c] = make_float2(z.x * amp, z.y * amp);
+  }
+}
+
+// inverse column transforms only (for the generator)
+__global__ __launch_bounds__(THREADS) void col_inv_kernel(MPArgs a) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, cl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, c0 = blockIdx.x * R;
+  load_tw(tw, a.tw256, t);
+  float2 *S = a.spec + field(pair);
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / R, cc = i % R;
+    L[cc * LP + pad(row)] = S[(size_t)row * NN + c0 + cc];
+  }
+  __syncthreads();
+  fft_stage_b<+1>(L + cl * LP, r);
+  __syncthreads();
+  fft_stage_a<+1>(L + cl * LP, r, tw);
+  __syncthreads();
+  for (int i = t; i < R * NN; i += THREADS) {
+    const int row = i / R, cc = i % R;
+    S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
+  }
+}
+
+// slopes (+ noise, valid subapertures) and node phase from the screen pair in PHI
+__global__ __launch_bounds__(THREADS) void gen_slopes_kernel(MPArgs a, GenArgs g) {
+  const int pair = blockIdx.y;
+  const uint64_t gp = g.first_pair + pair + (g.d_counter ? *g.d_counter / 2 : 0);
+  const float2 *P = a.phi + field(pair);
+  const int n = g.n, o = g.o, plane = n * n;
+  const bool hasB = 2 * pair + 1 < g.B;
+  float *sa = g.slopes + (size_t)(2 * pair) * 2 * plane;
+  for (int idx = blockIdx.x * THREADS + threadIdx.x; idx < plane; idx += gridDim.x * THREADS) {
+    const int i = idx / n, jj = idx - i * n, m = o + i, c = o + jj;
+    const float2 p00 = P[(size_t)m * NN + c], p01 = P[(size_t)m * NN + c + 1];
+    const float2 p10 = P[(size_t)(m + 1) * NN + c], p11 = P[(size_t)(m + 1) * NN + c + 1];
+    const float2 sx = make_float2(0.5f * ((p01.x - p00.x) + (p11.x - p10.x)), 0.5f * ((p01.y - p00.y) + (p11.y - p10.y)));
+    const float2 sy = make_float2(0.5f * ((p10.x - p00.x) + (p11.x - p01.x)), 0.5f * ((p10.y - p00.y) + (p11.y - p01.y)));
+    uint32_t r4[4];
+    philox_pair(uint32_t(gp), uint32_t(gp >> 32), uint32_t(idx), 1u, g.seed_lo, g.seed_hi, r4);
+    const float2 na = bm(r4[0], r4[1]), nb = bm(r4[2], r4[3]);
+    const float valid = g.mask[idx] ? 1.f : 0.f;
+    sa[idx] = valid * (sx.x + g.sigma * na.x);
+    sa[plane + idx] = valid * (sy.x + g.sigma * na.y);
+    if (hasB) {
+      sa[2 * plane + idx] = valid * (sx.y + g.sigma * nb.x);
+      sa[3 * plane + idx] = valid * (sy.y + g.sigma * nb.y);
+    }
+  }
+  if (g.phase) {
+    const int n1 = n + 1;
+    float *pa = g.phase + (size_t)(2 * pair) * n1 * n1;
+    for (int idx = blockIdx.x * THREADS + threadIdx.x; idx < n1 * n1; idx += gridDim.x * THREADS) {
+      const int i = idx / n1, jj = idx - i * n1;
+      const float2 v = P[(size_t)(o + i) * NN + o + jj];
+      pa[idx] = v.x;
+      if (hasB) pa[(size_t)n1 * n1 + idx] = v.y;
+    }
+  }
+}
+
+__global__ void mp_counter_add_kernel(uint64_t *c, uint64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c += v;
+}
+
+}  // namespace mp
+
+hipError_t multipass_generate(const MPArgs &a, const GenArgs &g, hipStream_t s) {
+  using namespace mp;
+  const int pairs = (g.B + 1) / 2;
+  const dim3 rows(NN / R, pairs), blk(THREADS);
+  hipLaunchKernelGGL(gen_spectrum_kernel, rows, blk, 0, s, a, g);
+  hipLaunchKernelGGL(col_inv_kernel, rows, blk, 0, s, a);
+  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
+  hipLaunchKernelGGL(gen_slopes_kernel, dim3(16, pairs), blk, 0, s, a, g);
+  if (g.d_counter) hipLaunchKernelGGL(mp_counter_add_kernel, dim3(1), dim3(64), 0, s, g.d_counter, uint64_t(2 * pairs));
+  return hipGetLastError();
+}
+
+}  // namespace fwr

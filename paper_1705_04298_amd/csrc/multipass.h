@@ -28,5 +28,7 @@ struct MPArgs {
 bool multipass_supported(int N);
 size_t multipass_workspace_bytes(int N, int n, int max_batch);
 hipError_t multipass_run(const MPArgs &a, bool extend, hipStream_t s);
+struct GenArgs;
+hipError_t multipass_generate(const MPArgs &a, const GenArgs &g, hipStream_t s);
 
 }  // namespace fwr

@@ -30,7 +30,8 @@ ONCHIP_GRIDS = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 128)
 EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set_stream",
             "fwr_plan_launch_info", "fwr_status_string", "fwr_extend_start", "fwr_reconstruct_start",
             "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
-            "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy")
+            "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
+            "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream")
 CNN_PARAMS = 47714
 
 
@@ -51,6 +52,17 @@ class FwrParams(ctypes.Structure):
         ("alpha_map", ctypes.POINTER(ctypes.c_double)),
         ("max_batch", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class FwrWork(ctypes.Structure):
+    _fields_ = [
+        ("plan", ctypes.c_void_p),
+        ("d_slopes", ctypes.c_void_p),
+        ("d_phase", ctypes.c_void_p),
+        ("d_start", ctypes.c_void_p),
+        ("d_resid", ctypes.c_void_p),
+        ("B", ctypes.c_int32),
     ]
 
 
@@ -105,8 +117,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_backward.restype = ctypes.c_int
     lib.fwr_cnn_adam_step.argtypes = [vp, f32]
     lib.fwr_cnn_adam_step.restype = ctypes.c_int
+    lib.fwr_cnn_set_stream.argtypes = [vp, vp]
+    lib.fwr_cnn_set_stream.restype = ctypes.c_int
     lib.fwr_cnn_destroy.argtypes = [vp]
     lib.fwr_cnn_destroy.restype = ctypes.c_int
+    lib.fwr_reconstruct_group.argtypes = [ctypes.POINTER(FwrWork), i32, vp]
+    lib.fwr_reconstruct_group.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    lib.fwr_generate.argtypes = [vp, u64, u64, vp, f32, f32, f32, vp, vp, i32]
+    lib.fwr_generate.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -148,6 +167,21 @@ def fwr_destroy(plan) -> int:
 
 def fwr_set_stream(plan, stream: int) -> int:
     return load().fwr_set_stream(plan, ctypes.c_void_p(stream))
+
+
+def fwr_reconstruct_group(items, stream: int) -> int:
+    """items: sequence of (plan handle, d_slopes, d_phase, d_start, d_resid, B) device pointers (0 = NULL)."""
+    arr = (FwrWork * max(1, len(items)))()
+    for i, (h, s, o, st, r, B) in enumerate(items):
+        arr[i].plan, arr[i].d_slopes, arr[i].d_phase = h, s or None, o or None
+        arr[i].d_start, arr[i].d_resid, arr[i].B = st or None, r or None, int(B)
+    return load().fwr_reconstruct_group(arr, len(items), ctypes.c_void_p(stream))
+
+
+def fwr_generate(plan, seed: int, first_frame: int, d_counter: int, r0: float, L0: float, sigma: float,
+                 d_slopes: int, d_phase: int, B: int) -> int:
+    return load().fwr_generate(plan, ctypes.c_uint64(seed), ctypes.c_uint64(first_frame), d_counter or None,
+                               float(r0), float(L0), float(sigma), d_slopes or None, d_phase or None, int(B))
 
 
 def fwr_plan_launch_info(plan):
@@ -250,6 +284,43 @@ class Plan:
     def launch_info(self):
         return fwr_plan_launch_info(self._h)
 
+    def generate(self, B: int, seed: int, first_frame: int = 0, r0: float = 0.15, L0: float = 25.0,
+                 sigma: float = 0.05, counter=None, slopes=None, phase=None, with_phase: bool = False):
+        """Synthetic frames on the device (fwr_generate): returns (slopes [B, 2, n, n], phase or None).
+
+        `counter`: optional int64 CUDA tensor of one element, the device frame counter."""
+        import torch
+        n = self.n_sub
+        if slopes is None:
+            slopes = torch.empty((B, 2, n, n), device="cuda", dtype=torch.float32)
+        self._check(slopes, (B, 2, n, n), "slopes")
+        if phase is None and with_phase:
+            phase = torch.empty((B, n + 1, n + 1), device="cuda", dtype=torch.float32)
+        if phase is not None:
+            self._check(phase, (B, n + 1, n + 1), "phase")
+        cp = 0
+        if counter is not None:
+            if not (isinstance(counter, torch.Tensor) and counter.is_cuda and counter.dtype == torch.int64
+                    and counter.numel() == 1):
+                raise TypeError("counter must be a one-element int64 CUDA tensor")
+            cp = counter.data_ptr()
+        st = fwr_generate(self._h, seed, first_frame, cp, r0, L0, sigma, slopes.data_ptr(),
+                          phase.data_ptr() if phase is not None else 0, B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_generate")
+        return slopes, phase
+
+    def set_stream(self, stream: Optional[int] = None):
+        """Rebind the plan to `stream` (default: torch's current stream), e.g. a capture stream."""
+        self.stream = _current_stream() if stream is None else int(stream)
+        st = fwr_set_stream(self._h, self.stream)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_set_stream")
+
+    @property
+    def handle(self):
+        return self._h
+
     def close(self):
         if getattr(self, "_h", None):
             fwr_destroy(self._h)
@@ -260,6 +331,24 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def reconstruct_group(work, stream: Optional[int] = None):
+    """Several (plan, slopes, out, start, resid) items in one fwr_reconstruct_group call.
+
+    `work`: sequence of tuples (Plan, slopes, out, start or None, resid or None); tensors as
+    Plan.reconstruct.  Items run concurrently; the call is ordered on `stream` (default: torch's
+    current stream)."""
+    items = []
+    for plan, slopes, out, start, resid in work:
+        B = slopes.shape[0]
+        plan._check(slopes, (B, 2, plan.n_sub, plan.n_sub), "slopes")
+        plan._check(out, (B, plan.n_sub + 1, plan.n_sub + 1), "out")
+        sp, rp = plan._start_args(start, resid, B)
+        items.append((plan.handle, slopes.data_ptr(), out.data_ptr(), sp, rp, B))
+    st = fwr_reconstruct_group(items, _current_stream() if stream is None else int(stream))
+    if st != FWR_OK:
+        raise FwrError(st, "fwr_reconstruct_group")
 
 
 class CNN:
@@ -315,6 +404,13 @@ class CNN:
         if st != FWR_OK:
             raise FwrError(st, "fwr_cnn_backward")
         return float(loss.value)
+
+    def set_stream(self, stream: Optional[int] = None):
+        """Rebind to `stream` (default: torch's current stream), e.g. a capture stream."""
+        self.stream = _current_stream() if stream is None else int(stream)
+        st = load().fwr_cnn_set_stream(self._h, ctypes.c_void_p(self.stream))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_set_stream")
 
     def adam_step(self, lr: float):
         st = load().fwr_cnn_adam_step(self._h, float(lr))
