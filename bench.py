@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cnn", action="store_true", help="uneven workload: plain start for the 40x40 frames")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default launch shape")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = up to 16; use 1 under a profiler)")
@@ -166,8 +167,10 @@ def main():
     mask = I.pupil_mask(N_SUB)
     plan = fwr.Plan(N_SUB, N_GRID, mask, n_iter=N_ITER, periodic=True, gamma=1.0,
                     noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=0.2, max_batch=args.batch)
-    threads, fpg, lds = plan.launch_info()
     x = torch.from_numpy(slopes).cuda()
+    if not args.no_autotune:
+        plan.autotune(args.batch)  # launch shape (frames per workgroup) by timing
+    threads, fpg, lds = plan.launch_info()
     out = torch.empty((args.batch, N_SUB + 1, N_SUB + 1), device="cuda", dtype=torch.float32)
     for _ in range(args.warmup):
         plan.reconstruct(x, out)

@@ -112,6 +112,20 @@ fwr_status fwr_destroy(fwr_plan_t plan);
 /* Change the stream later calls enqueue on. */
 fwr_status fwr_set_stream(fwr_plan_t plan, void *stream);
 
+/* Launch shape of the on-chip kernel (grids up to 128 x 128): frames per
+ * workgroup, 2 (one frame pair) or 4, 8, 16 where the kernel is built for it and the
+ * workgroup's LDS fits (FWR_E_UNSUPPORTED otherwise; FWR_E_INVAL for odd or < 2).
+ * Results do not depend on it.  Plans start from the choice autotuned earlier in the
+ * process for the same device, N, n, n_iter and Eq. 5 mode, else from a rule that
+ * balances the waves of a workgroup over the four SIMDs of a CU. */
+fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
+
+/* Autotuner: times every frames-per-workgroup choice of the plan on B frames (B <=
+ * max_batch; device scratch is allocated and freed here) on the plan's stream,
+ * synchronously, keeps the fastest in the plan and for later plans of the same shape,
+ * and returns it in *frames_per_group (may be NULL).  Not for use under graph capture. */
+fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group);
+
 /* Launch shape of the reconstruction kernel, for reporting: threads per
  * workgroup, frames per workgroup, dynamic LDS bytes per workgroup. */
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,

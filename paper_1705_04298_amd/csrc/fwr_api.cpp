@@ -9,7 +9,9 @@
 #include <vector>
 
 #include "../../include/fwr.h"
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "gen.h"
 #include "multipass.h"
@@ -39,6 +41,7 @@ struct fwr_plan_s {
   const float *h_final = nullptr;
   const float2 *tw_lane = nullptr;
   const uint32_t *codes = nullptr;
+  int pairs = 1;  // frame pairs per workgroup of the on-chip kernel
   // multi-pass path (N = 256)
   bool multipass = false;
   fwr::MPArgs mp{};
@@ -49,6 +52,41 @@ struct fwr_plan_s {
 namespace {
 
 bool valid(fwr_plan_t p) { return p != nullptr && p->magic == kMagic; }
+
+// frame pairs per workgroup that the on-chip kernel is built for
+constexpr int kPairsOptions[] = {1, 2, 4, 8};
+
+// Autotuned choices, per device and problem shape (process-wide).
+struct TuneKey {
+  int device, N, n, n_iter;
+  bool each;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(device, N, n, n_iter, each) < std::tie(o.device, o.N, o.n, o.n_iter, o.each);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned[TuneKey{device, N, n, n_iter, each}] = pairs;
+}
+
+// The tuned choice when there is one.  Otherwise: two pairs when one pair's waves
+// number 4k + 1 (k >= 1), where a lone workgroup leaves one SIMD with twice the waves
+// of the others and every phase waits for it (N = 80: 5 waves; two pairs make
+// 3, 3, 2, 2); one pair elsewhere, where larger groups measured slower (they lower the
+// register budget per wave).
+int tuned_pairs(int device, int N, int n, int n_iter, bool each) {
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(TuneKey{device, N, n, n_iter, each});
+    if (it != g_tuned.end()) return it->second;
+  }
+  const int waves = (fwr::onchip_threads(N, 1) + 63) / 64;
+  if (waves > 4 && waves % 4 == 1 && fwr::onchip_pairs_ok(N, n, 2, each)) return 2;
+  return 1;
+}
 
 // Squared Fried transfer function |G_x|^2 + |G_y|^2 = 4 (u^2 + v^2),
 // u = sin(pi k/N) cos(pi l/N), v = sin(pi l/N) cos(pi k/N).
@@ -121,7 +159,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   if (fwr::multipass_supported(N)) return plan_multipass(p, out);
   if (!fwr::onchip_supported(N)) return FWR_E_UNSUPPORTED;
 
-  const int T = N / 4, threads = fwr::onchip_threads(N);
+  const int T = N / 4, threads = fwr::onchip_threads(N, 1);
   static const int beta[4] = {0, 2, 1, 3};
 
   // host tables
@@ -165,13 +203,19 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
         codes[(size_t)(k / 8) * threads + 4 * m + jj] |= c << (4 * (k % 8));
       }
 
-  if (fwr::onchip_lds_bytes(N, n) > 160 * 1024) return FWR_E_UNSUPPORTED;
+  const bool each = p.periodic_each_iter != 0;
+  if (!fwr::onchip_pairs_ok(N, n, 1, each)) return FWR_E_UNSUPPORTED;
   auto *plan = new (std::nothrow) fwr_plan_s();
   if (plan == nullptr) return FWR_E_NOMEM;
-  if (hipGetDevice(&plan->device) != hipSuccess || fwr::onchip_prepare(N, n) != hipSuccess) {
+  bool prepared = hipGetDevice(&plan->device) == hipSuccess;
+  for (int pairs : kPairsOptions)
+    if (prepared && fwr::onchip_pairs_ok(N, n, pairs, each))
+      prepared = fwr::onchip_prepare(N, n, pairs) == hipSuccess;
+  if (!prepared) {
     delete plan;
     return FWR_E_DEVICE;
   }
+  plan->pairs = tuned_pairs(plan->device, N, n, p.n_iter, each);
   const size_t b_h = h_loop.size() * sizeof(float);
   const size_t b_tw = tw.size() * sizeof(float2);
   const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
@@ -245,7 +289,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
   a.start = start;
   a.resid = resid;
-  return fwr::onchip_launch(plan->N, a, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  return fwr::onchip_launch(plan->N, a, st, plan->pairs) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
 fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
@@ -351,9 +395,69 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
     if (lds_bytes) *lds_bytes = 0;
     return FWR_OK;
   }
-  if (threads) *threads = fwr::onchip_threads(plan->N);
-  if (frames_per_group) *frames_per_group = 2;
-  if (lds_bytes) *lds_bytes = fwr::onchip_lds_bytes(plan->N, plan->n);
+  if (threads) *threads = fwr::onchip_threads(plan->N, plan->pairs);
+  if (frames_per_group) *frames_per_group = 2 * plan->pairs;
+  if (lds_bytes) *lds_bytes = fwr::onchip_lds_bytes(plan->N, plan->n, plan->pairs);
+  return FWR_OK;
+}
+
+fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (plan->multipass) return frames_per_group == 2 ? FWR_OK : FWR_E_UNSUPPORTED;
+  if (frames_per_group < 2 || frames_per_group % 2 != 0) return FWR_E_INVAL;
+  const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
+  if (!fwr::onchip_pairs_ok(plan->N, plan->n, frames_per_group / 2, each)) return FWR_E_UNSUPPORTED;
+  plan->pairs = frames_per_group / 2;
+  return FWR_OK;
+}
+
+fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (B < 1 || B > plan->max_batch) return FWR_E_INVAL;
+  if (plan->multipass) {
+    if (frames_per_group) *frames_per_group = 2;
+    return FWR_OK;
+  }
+  const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
+  const int n = plan->n, N = plan->N;
+  // the kernels' work does not depend on the slope values: time them on zeros
+  float *d_in = nullptr, *d_out = nullptr;
+  const size_t in_bytes = (size_t)B * 2 * n * n * sizeof(float);
+  const size_t out_bytes = (size_t)B * (n + 1) * (n + 1) * sizeof(float);
+  if (hipMalloc(reinterpret_cast<void **>(&d_in), in_bytes) != hipSuccess) return FWR_E_NOMEM;
+  if (hipMalloc(reinterpret_cast<void **>(&d_out), out_bytes) != hipSuccess) {
+    (void)hipFree(d_in);
+    return FWR_E_NOMEM;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+            hipMemsetAsync(d_in, 0, in_bytes, plan->stream) == hipSuccess;
+  const int before = plan->pairs;
+  int best = before;
+  float best_ms = 0.f;
+  for (int pairs : kPairsOptions) {
+    if (!ok) break;
+    if (!fwr::onchip_pairs_ok(N, n, pairs, each)) continue;
+    plan->pairs = pairs;
+    float ms = 0.f;
+    ok = run(plan, d_in, d_out, B, false) == FWR_OK && hipEventRecord(e0, plan->stream) == hipSuccess;
+    for (int r = 0; r < 3 && ok; ++r) ok = run(plan, d_in, d_out, B, false) == FWR_OK;
+    ok = ok && hipEventRecord(e1, plan->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    // a larger group must win by more than timing noise
+    if (ok && (best_ms == 0.f || ms < 0.97f * best_ms)) {
+      best = pairs;
+      best_ms = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d_in);
+  (void)hipFree(d_out);
+  plan->pairs = ok ? best : before;
+  if (!ok) return FWR_E_DEVICE;
+  remember_pairs(plan->device, N, n, plan->n_iter, each, best);
+  if (frames_per_group) *frames_per_group = 2 * best;
   return FWR_OK;
 }
 

@@ -52,13 +52,26 @@ struct Onchip {
   // (n+1) * N complex) so that two workgroups share a CU; N = 128 keeps it in
   // registers (one workgroup per CU).
   static constexpr bool F0_IN_LDS = N <= 80;
-  static constexpr int STATIC_LDS_BYTES =
-      (TILE + 2 * N + T * 4) * 8 + (THREADS % 64 == 0 ? 16 * (THREADS / 64) : 16 * THREADS);
-  static int lds_bytes(int n) { return STATIC_LDS_BYTES + (F0_IN_LDS ? (n + 1) * PITCH * 8 : 0); }
-  // Register budget: two workgroups per CU (80 KB of LDS each at N = 80) put
-  // three waves on some SIMDs, i.e. at most 168 VGPRs.  The iteration loop fits
-  // without spills; the once-per-frame final step spills a few values.
   static constexpr int WAVES_PER_SIMD = N <= 80 ? FWR_ONCHIP_MIN_WAVES : 2;
+  // residual partials per frame pair: one set per wave (full waves) or per thread
+  static constexpr int RED = THREADS % 64 == 0 ? 4 * (THREADS / 64) : 4 * THREADS;
+};
+
+// PAIRS frame pairs per workgroup (PAIRS x 4N threads).  The workgroup's barriers
+// make every phase wait for its busiest SIMD; 4N threads make 5 waves at N = 80,
+// i.e. 2 waves on one SIMD and 1 on the others, while 2 pairs make 10 waves
+// (3, 3, 2, 2).  Registers must then allow ceil(waves / 4) waves per SIMD.
+template <int N, int PAIRS>
+struct Group {
+  static constexpr int THREADS = PAIRS * Onchip<N>::THREADS;
+  static constexpr int WAVES = (THREADS + 63) / 64;
+  static constexpr int WAVES_PER_SIMD =
+      (WAVES + 3) / 4 > Onchip<N>::WAVES_PER_SIMD ? (WAVES + 3) / 4 : Onchip<N>::WAVES_PER_SIMD;
+  static constexpr int STATIC_LDS_BYTES = PAIRS * (Onchip<N>::TILE + 2 * N) * 8 + Onchip<N>::T * 4 * 8 +
+                                          PAIRS * Onchip<N>::RED * 4;
+  static int lds_bytes(int n) {
+    return STATIC_LDS_BYTES + (Onchip<N>::F0_IN_LDS ? PAIRS * (n + 1) * Onchip<N>::PITCH * 8 : 0);
+  }
 };
 
 // c ? a : b on the bit patterns: exact, and both operands are always computed, so
@@ -68,32 +81,40 @@ __device__ __forceinline__ float select_bits(bool c, float a, float b) {
   return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
 }
 
-template <int N, bool EACH>
-__global__ __launch_bounds__(Onchip<N>::THREADS)
-__attribute__((amdgpu_waves_per_eu(Onchip<N>::WAVES_PER_SIMD)))
+// EACH: Eq. 5 after every iteration (flag kFlagPeriodicEach)
+template <int N, bool EACH, int PAIRS>
+__global__ __launch_bounds__((Group<N, PAIRS>::THREADS))
+__attribute__((amdgpu_waves_per_eu(Group<N, PAIRS>::WAVES_PER_SIMD)))
 void gerchberg_onchip_kernel(OnchipArgs a) {
   using C = Onchip<N>;
   constexpr int T = C::T;
   constexpr int P = C::PITCH;
-  __shared__ float2 buf[C::TILE];
-  __shared__ float2 sums[2 * N];  // Eq. 5: column sums C_n, then row sums R_m
-  // residual partial sums: one set per wave (full waves) or per thread (N < 16)
+  __shared__ float2 buf_all[PAIRS * C::TILE];
+  __shared__ float2 sums_all[PAIRS * 2 * N];  // Eq. 5: column sums C_n, then row sums R_m
   constexpr bool FULL_WAVES = C::THREADS % 64 == 0;
-  __shared__ float red[FULL_WAVES ? 4 * (C::THREADS / 64) : 4 * C::THREADS];
+  __shared__ float red_all[PAIRS * C::RED];
   __shared__ float2 tw[T * 4];
-  extern __shared__ float2 f0rows[];  // [(n+1)][PITCH], lane-blocked like the tile rows
+  extern __shared__ float2 f0rows_all[];  // PAIRS x [(n+1)][PITCH], lane-blocked like the tile rows
 
-  const int t = threadIdx.x;
+  // this thread's frame pair within the workgroup and its LDS
+  const int half = PAIRS == 1 ? 0 : int(threadIdx.x) / C::THREADS;
+  const int t = int(threadIdx.x) - half * C::THREADS;
+  float2 *const buf = buf_all + half * C::TILE;
+  float2 *const sums = sums_all + half * 2 * N;
+  float *const red = red_all + half * C::RED;
+  float2 *const f0rows = f0rows_all + (C::F0_IN_LDS ? half * (a.n + 1) * P : 0);
   const int line = t >> 2;
   const int j = t & 3;
   const QuadLane q(j);
-  const int fa = 2 * blockIdx.x;
-  const bool hasB = fa + 1 < a.B;
+  // a pair past the batch (last workgroup) computes on pair 0's input and writes nothing
+  const bool active = 2 * (PAIRS * int(blockIdx.x) + half) < a.B;
+  const int fa = active ? 2 * (PAIRS * int(blockIdx.x) + half) : 0;
+  const bool hasB = active && fa + 1 < a.B;
   const int n = a.n, o = a.o;
   const int up = line == 0 ? N - 1 : line - 1;    // row m - 1
   const int dn = line == N - 1 ? 0 : line + 1;    // row m + 1
 
-  for (int i = t; i < T * 4; i += C::THREADS) tw[i] = a.tw_lane[i];
+  for (int i = threadIdx.x; i < T * 4; i += Group<N, PAIRS>::THREADS) tw[i] = a.tw_lane[i];
 
   // ---- per-node constants: out-of-pupil cell bits and the in-pupil forcing F0
   const int plane = n * n;
@@ -146,7 +167,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const float rowf = in_rows ? 1.f : 0.f;
 
   const bool want_resid = a.resid != nullptr && a.n_iter > 0;
-  if (a.resid != nullptr && a.n_iter == 0 && t == 0) {
+  if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) {
     a.resid[fa] = 0.f;
     if (hasB) a.resid[fa + 1] = 0.f;
   }
@@ -237,11 +258,17 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   // periodised) slopes themselves are written out instead (returns true).
   //
   // Eq. 5 only rewrites s_x on column N-1 and s_y on row N-1: with
-  // R_m = sum_n s_x(m, n) and C_n = sum_m s_y(m, n) (all cells, as measured /
-  // extrapolated), s_x(m, N-1) drops by R_m and s_y(N-1, n) by C_n.  Through the
-  // adjoint stencil this moves q2 only on the border node lines:
+  // R_m = sum_n s_x(m, n) and C_n = sum_m s_y(m, n), s_x(m, N-1) drops by R_m and
+  // s_y(N-1, n) by C_n.  Through the adjoint stencil this moves q2 only on the
+  // border node lines:
   //   node (m, 0)   by -(R_m + R_{m-1}),   node (m, N-1) by +(R_m + R_{m-1}),
   //   node (0, n)   by -(C_n + C_{n-1}),   node (N-1, n) by +(C_n + C_{n-1}).
+  // Outside the pupil the slopes are the model slopes of the periodic phase, whose
+  // sums along a full row (x) or column (y) telescope to zero, so R_m and C_n are the
+  // sums of the in-pupil misfits (measured - model) alone.  When the step runs once
+  // (F0 is read for the last time here) the y misfits take the place of F0 (the
+  // thread's own LDS slots or registers); otherwise they are held in registers.
+  constexpr bool EY_IN_F0 = !EACH;
   auto final_step = [&](float2 *x, bool fix, bool write) -> bool {
 #pragma unroll
     for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
@@ -249,50 +276,48 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     const unsigned wrow = unsigned(line >= o && line < o + n ? line - o : 0) * unsigned(n);
     const size_t gplane = (size_t)N * N;
     float *ea = a.out + (size_t)fa * 2 * gplane;  // extended slopes of frame A (write mode)
-    float2 rowacc = make_float2(0.f, 0.f), sx_last = make_float2(0.f, 0.f);
+    float2 rowacc = make_float2(0.f, 0.f);
     float ra = 0.f, rb = 0.f, na = 0.f, nb = 0.f;  // in-pupil misfit and measurement energy
-    float2 DY[T];
+    float2 DY[EY_IN_F0 ? 1 : T];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       const int nn = 4 * k + j;
       const uint32_t c4 = code_of(k);
       const bool meas = !(c4 & 1u);
       const unsigned widx = wrow + unsigned(nn >= o && nn < o + n ? nn - o : 0);
-      const float mxa = sa[widx], mya = sa[uplane + widx];
-      const float mxb = sbb[widx] * bflag, myb = sbb[uplane + widx] * bflag;
+      // measured slopes, exactly zero outside the pupil (whatever the input holds there)
+      const float mxa = select_bits(meas, sa[widx], 0.f), mya = select_bits(meas, sa[uplane + widx], 0.f);
+      const float mxb = select_bits(meas, sbb[widx] * bflag, 0.f);
+      const float myb = select_bits(meas, sbb[uplane + widx] * bflag, 0.f);
       const int sp = slot_p(k), sm = slot_m(k);
       const float2 ph = x[k];
-      const float2 b = buf[line * P + sp];  // (m, n+1)
+      const float2 b = buf[line * P + sp];       // (m, n+1)
       const float2 c = buf[dn * P + T * j + k];  // (m+1, n)
-      const float2 d1 = buf[dn * P + sp];  // (m+1, n+1)
-      const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
-      const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
-      const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
+      const float2 d1 = buf[dn * P + sp];        // (m+1, n+1)
       // cell (m, n): s_x = (b - a + d - c) / 2, s_y = (c - a + d - b) / 2
       const float2 gx = make_float2(0.5f * ((b.x - ph.x) + (d1.x - c.x)), 0.5f * ((b.y - ph.y) + (d1.y - c.y)));
       const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
-      const float2 sxk = make_float2(select_bits(meas, mxa, gx.x), select_bits(meas, mxb, gx.y));
-      const float2 syk = make_float2(select_bits(meas, mya, gy.x), select_bits(meas, myb, gy.y));
+      const float2 ex = make_float2(select_bits(meas, mxa - gx.x, 0.f), select_bits(meas, mxb - gx.y, 0.f));
+      const float2 ey = make_float2(select_bits(meas, mya - gy.x, 0.f), select_bits(meas, myb - gy.y, 0.f));
       if (want_resid) {
-        const float mf = meas ? 1.f : 0.f;
-        const float ex = gx.x - mxa, ey = gy.x - mya, fx = gx.y - mxb, fy = gy.y - myb;
-        ra = fmaf(mf, ex * ex + ey * ey, ra);
-        rb = fmaf(mf, fx * fx + fy * fy, rb);
-        na = fmaf(mf, mxa * mxa + mya * mya, na);
-        nb = fmaf(mf, mxb * mxb + myb * myb, nb);
+        ra = fmaf(ex.x, ex.x, fmaf(ey.x, ey.x, ra));
+        rb = fmaf(ex.y, ex.y, fmaf(ey.y, ey.y, rb));
+        na = fmaf(mxa, mxa, fmaf(mya, mya, na));
+        nb = fmaf(mxb, mxb, fmaf(myb, myb, nb));
       }
-      rowacc = cadd(rowacc, sxk);
-      DY[k] = syk;
-      if (k == T - 1) sx_last = sxk;
-      if (write) {
+      rowacc = cadd(rowacc, ex);
+      if (write && active) {
         const size_t idx = (size_t)line * N + nn;
-        ea[idx] = sxk.x;
-        ea[gplane + idx] = syk.x;
+        ea[idx] = select_bits(meas, mxa, gx.x);
+        ea[gplane + idx] = select_bits(meas, mya, gy.x);
         if (hasB) {
-          ea[2 * gplane + idx] = sxk.y;
-          ea[3 * gplane + idx] = syk.y;
+          ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
+          ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
         }
       } else {
+        const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
+        const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
+        const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
         float2 r;
         if constexpr (C::F0_IN_LDS) {
           const float2 fv = f0rows[f0row + k];
@@ -311,6 +336,13 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         r.x = fmaf(w4, ph.x - d4.x, r.x);
         r.y = fmaf(w4, ph.y - d4.y, r.y);
         x[k] = r;
+      }
+      if constexpr (EY_IN_F0 && C::F0_IN_LDS) {
+        if (in_rows) f0rows[f0row + k] = ey;  // after this thread's last read of the slot
+      } else if constexpr (EY_IN_F0) {
+        f0[k] = ey;
+      } else {
+        DY[k] = ey;
       }
       if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
@@ -333,7 +365,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         red[4 * slot + 3] = nb;
       }
       __syncthreads();
-      if (t == 0) {
+      if (t == 0 && active) {
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
         for (int w = 0; w < PARTS; ++w) {
           s0 += red[4 * w];
@@ -351,32 +383,36 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       rowacc.y += dpp_xor1(rowacc.y);
       rowacc.x += dpp_xor2(rowacc.x);
       rowacc.y += dpp_xor2(rowacc.y);
-      __syncthreads();
+      __syncthreads();  // every neighbour read of the tile and every misfit store is done
+      if constexpr (!(EY_IN_F0 && C::F0_IN_LDS)) {
 #pragma unroll
-      for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = DY[k];
+        for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = EY_IN_F0 ? f0[k] : DY[k];
+      }
       if (j == 0) sums[N + line] = rowacc;
       __syncthreads();
-      if (t < N) {  // C_n in a fixed order (deterministic)
+      if (t < N) {  // C_n over the pupil rows, in a fixed order (deterministic)
         float2 cs = make_float2(0.f, 0.f);
         const int slot = T * (t & 3) + (t >> 2);
-        for (int m = 0; m < N; ++m) cs = cadd(cs, buf[m * P + slot]);
+        for (int r = 0; r < n; ++r)
+          cs = cadd(cs, EY_IN_F0 && C::F0_IN_LDS ? f0rows[r * P + slot] : buf[(o + r) * P + slot]);
         sums[t] = cs;
       }
       __syncthreads();
       const float2 Rm = sums[N + line], Rm1 = sums[N + up];
       if (write) {
-        if (j == 3) {  // s_x(m, N-1) -= R_m
+        // the thread re-reads the slopes it wrote above (same-thread order)
+        if (active && j == 3) {  // s_x(m, N-1) -= R_m
           const size_t idx = (size_t)line * N + (N - 1);
-          ea[idx] = sx_last.x - Rm.x;
-          if (hasB) ea[2 * gplane + idx] = sx_last.y - Rm.y;
+          ea[idx] -= Rm.x;
+          if (hasB) ea[2 * gplane + idx] -= Rm.y;
         }
-        if (line == N - 1) {  // s_y(N-1, n) -= C_n
+        if (active && line == N - 1) {  // s_y(N-1, n) -= C_n
 #pragma unroll
           for (int k = 0; k < T; ++k) {
             const size_t idx = (size_t)line * N + 4 * k + j;
             const float2 cn = sums[4 * k + j];
-            ea[gplane + idx] = DY[k].x - cn.x;
-            if (hasB) ea[3 * gplane + idx] = DY[k].y - cn.y;
+            ea[gplane + idx] -= cn.x;
+            if (hasB) ea[3 * gplane + idx] -= cn.y;
           }
         }
       } else {
@@ -461,7 +497,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   solve(x, a.h_final);
 
   // (n+1) x (n+1) node window
-  if (line >= o && line <= o + n) {
+  if (active && line >= o && line <= o + n) {
     float *oa = a.out + (size_t)fa * (n + 1) * (n + 1);
     float *ob = oa + (size_t)(n + 1) * (n + 1);
 #pragma unroll
@@ -476,27 +512,91 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   }
 }
 
-template <int N>
-hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s) {
-  const int groups = (a.B + 1) / 2;
-  const size_t dyn = Onchip<N>::F0_IN_LDS ? size_t(a.n + 1) * Onchip<N>::PITCH * 8 : 0;
-  if (a.flags & kFlagPeriodicEach)
-    hipLaunchKernelGGL((gerchberg_onchip_kernel<N, true>), dim3(groups), dim3(Onchip<N>::THREADS), dyn, s, a);
-  else
-    hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false>), dim3(groups), dim3(Onchip<N>::THREADS), dyn, s, a);
-  return hipGetLastError();
+// PAIRS > 1 is instantiated for the kernel without per-iteration Eq. 5, within 1024
+// threads per workgroup
+template <int N, int PAIRS>
+constexpr bool pairs_instantiated() {
+  return PAIRS == 1 || (Group<N, PAIRS>::THREADS <= 1024 && N <= 80);
+}
+
+template <int N, int PAIRS>
+hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
+  if constexpr (!pairs_instantiated<N, PAIRS>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const int groups = ((a.B + 1) / 2 + PAIRS - 1) / PAIRS;
+    const size_t dyn = Onchip<N>::F0_IN_LDS ? size_t(PAIRS) * (a.n + 1) * Onchip<N>::PITCH * 8 : 0;
+    const dim3 grid(groups), block(Group<N, PAIRS>::THREADS);
+    if ((a.flags & kFlagPeriodicEach) != 0) {
+      if constexpr (PAIRS == 1)
+        hipLaunchKernelGGL((gerchberg_onchip_kernel<N, true, 1>), grid, block, dyn, s, a);
+      else
+        return hipErrorInvalidValue;
+    } else {
+      hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false, PAIRS>), grid, block, dyn, s, a);
+    }
+    return hipGetLastError();
+  }
 }
 
 template <int N>
-hipError_t prepare_onchip(int n) {
-  // dynamic LDS above the default 64 KiB window must be requested explicitly
-  const int dyn = Onchip<N>::F0_IN_LDS ? (n + 1) * Onchip<N>::PITCH * 8 : 0;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-  return e;
+hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s, int pairs) {
+  switch (pairs) {
+    case 1: return launch_pairs<N, 1>(a, s);
+    case 2: return launch_pairs<N, 2>(a, s);
+    case 4: return launch_pairs<N, 4>(a, s);
+    case 8: return launch_pairs<N, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int PAIRS>
+hipError_t prepare_pairs(int n) {
+  if constexpr (!pairs_instantiated<N, PAIRS>()) {
+    return hipSuccess;
+  } else {
+    // dynamic LDS above the default 64 KiB window must be requested explicitly
+    const int dyn = Onchip<N>::F0_IN_LDS ? PAIRS * (n + 1) * Onchip<N>::PITCH * 8 : 0;
+    const void *fns[2] = {reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS>),
+                          PAIRS == 1 ? reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true, 1>)
+                                     : nullptr};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      if (fns[i]) e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    return e;
+  }
+}
+
+template <int N>
+hipError_t prepare_onchip(int n, int pairs) {
+  switch (pairs) {
+    case 1: return prepare_pairs<N, 1>(n);
+    case 2: return prepare_pairs<N, 2>(n);
+    case 4: return prepare_pairs<N, 4>(n);
+    case 8: return prepare_pairs<N, 8>(n);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+bool pairs_ok(int n, int pairs, bool each) {
+  bool inst = false;
+  switch (pairs) {
+    case 1: inst = true; break;
+    case 2: inst = pairs_instantiated<N, 2>(); break;
+    case 4: inst = pairs_instantiated<N, 4>(); break;
+    case 8: inst = pairs_instantiated<N, 8>(); break;
+    default: return false;
+  }
+  if (!inst || (each && pairs != 1)) return false;
+  int bytes = 0;
+  switch (pairs) {
+    case 1: bytes = Group<N, 1>::lds_bytes(n); break;
+    case 2: bytes = Group<N, 2>::lds_bytes(n); break;
+    case 4: bytes = Group<N, 4>::lds_bytes(n); break;
+    case 8: bytes = Group<N, 8>::lds_bytes(n); break;
+  }
+  return bytes <= 160 * 1024;
 }
 
 #define FWR_ONCHIP_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(128)
@@ -510,28 +610,45 @@ bool onchip_supported(int N) {
   }
 }
 
-int onchip_threads(int N) { return 4 * N; }
-int onchip_lds_bytes(int N, int n) {
+int onchip_threads(int N, int pairs) { return 4 * N * pairs; }
+int onchip_lds_bytes(int N, int n, int pairs) {
   switch (N) {
-#define FWR_CASE(NN) case NN: return Onchip<NN>::lds_bytes(n);
+#define FWR_CASE(NN)                                   \
+  case NN:                                             \
+    switch (pairs) {                                   \
+      case 1: return Group<NN, 1>::lds_bytes(n);       \
+      case 2: return Group<NN, 2>::lds_bytes(n);       \
+      case 4: return Group<NN, 4>::lds_bytes(n);       \
+      case 8: return Group<NN, 8>::lds_bytes(n);       \
+      default: return 0;                               \
+    }
     FWR_ONCHIP_SIZES(FWR_CASE)
 #undef FWR_CASE
     default: return 0;
   }
 }
 
-hipError_t onchip_prepare(int N, int n) {
+bool onchip_pairs_ok(int N, int n, int pairs, bool each) {
   switch (N) {
-#define FWR_CASE(NN) case NN: return prepare_onchip<NN>(n);
+#define FWR_CASE(NN) case NN: return pairs_ok<NN>(n, pairs, each);
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return false;
+  }
+}
+
+hipError_t onchip_prepare(int N, int n, int pairs) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return prepare_onchip<NN>(n, pairs);
     FWR_ONCHIP_SIZES(FWR_CASE)
 #undef FWR_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s) {
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs) {
   switch (N) {
-#define FWR_CASE(NN) case NN: return launch_onchip<NN>(a, s);
+#define FWR_CASE(NN) case NN: return launch_onchip<NN>(a, s, pairs);
     FWR_ONCHIP_SIZES(FWR_CASE)
 #undef FWR_CASE
     default: return hipErrorInvalidValue;

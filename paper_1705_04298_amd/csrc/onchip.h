@@ -23,10 +23,12 @@ struct OnchipArgs {
   int B, n, o, n_iter, flags;
 };
 
+// `pairs`: frame pairs per workgroup (1, 2, 4, 8; see onchip_pairs_ok)
 bool onchip_supported(int N);
-int onchip_threads(int N);
-int onchip_lds_bytes(int N, int n);   // per workgroup, static + dynamic
-hipError_t onchip_prepare(int N, int n); // once per plan, before the first launch
-hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s);
+bool onchip_pairs_ok(int N, int n, int pairs, bool periodic_each);  // instantiated and fits the LDS
+int onchip_threads(int N, int pairs);                  // per workgroup
+int onchip_lds_bytes(int N, int n, int pairs);         // per workgroup, static + dynamic
+hipError_t onchip_prepare(int N, int n, int pairs);    // before the first launch with `pairs`
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs);
 
 }  // namespace fwr

@@ -31,7 +31,8 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_plan_launch_info", "fwr_status_string", "fwr_extend_start", "fwr_reconstruct_start",
             "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
-            "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream")
+            "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
+            "fwr_plan_autotune")
 CNN_PARAMS = 47714
 
 
@@ -121,6 +122,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_set_stream.restype = ctypes.c_int
     lib.fwr_cnn_destroy.argtypes = [vp]
     lib.fwr_cnn_destroy.restype = ctypes.c_int
+    lib.fwr_plan_set_group.argtypes = [vp, i32]
+    lib.fwr_plan_set_group.restype = ctypes.c_int
+    lib.fwr_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.fwr_plan_autotune.restype = ctypes.c_int
     lib.fwr_reconstruct_group.argtypes = [ctypes.POINTER(FwrWork), i32, vp]
     lib.fwr_reconstruct_group.restype = ctypes.c_int
     u64 = ctypes.c_uint64
@@ -309,6 +314,20 @@ class Plan:
         if st != FWR_OK:
             raise FwrError(st, "fwr_generate")
         return slopes, phase
+
+    def set_group(self, frames_per_group: int):
+        """Frames per workgroup of the on-chip kernel (fwr_plan_set_group)."""
+        st = load().fwr_plan_set_group(self._h, int(frames_per_group))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_plan_set_group")
+
+    def autotune(self, B: Optional[int] = None) -> int:
+        """Time every launch shape on B frames, keep the fastest; returns frames per workgroup."""
+        out = ctypes.c_int32()
+        st = load().fwr_plan_autotune(self._h, int(B or self.max_batch), ctypes.byref(out))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_plan_autotune")
+        return out.value
 
     def set_stream(self, stream: Optional[int] = None):
         """Rebind the plan to `stream` (default: torch's current stream), e.g. a capture stream."""
