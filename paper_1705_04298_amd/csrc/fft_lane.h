@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <numeric>
 #include <type_traits>
 #include <utility>
 
@@ -160,6 +161,13 @@ __device__ __forceinline__ void bfly5(float2 *x) {
   x[3] = csub(a2, mul_i<DIR>(b2));
 }
 
+// inverse of a modulo m (a, m coprime; m = 1 gives 0)
+constexpr int modinv(int a, int m) {
+  for (int x = 0; x < m; ++x)
+    if ((a * x) % m == 1 % m) return x;
+  return 0;
+}
+
 template <int L>
 constexpr int first_radix() {
   if constexpr (L % 4 == 0) return 4;
@@ -181,6 +189,26 @@ __device__ __forceinline__ void dft(float2 *x) {
     bfly4<DIR>(x);
   } else if constexpr (L == 5) {
     bfly5<DIR>(x);
+  } else if constexpr (std::gcd(first_radix<L>(), L / first_radix<L>()) == 1) {
+    // coprime factors L = R M: prime-factor (Good-Thomas) algorithm, no twiddles.
+    // Input n = (M n1 + R n2) mod L, output k = (M M' k1 + R R' k2) mod L with
+    // M M' = 1 (mod R), R R' = 1 (mod M); then W_L^(n k) = W_R^(n1 k1) W_M^(n2 k2).
+    constexpr int R = first_radix<L>();
+    constexpr int M = L / R;
+    constexpr int Mi = modinv(M % R, R), Ri = modinv(R % M, M);
+    float2 s[R][M];
+    static_for<0, R>([&](auto r) {
+      static_for<0, M>([&](auto i) { s[r][i] = x[(M * decltype(r)::value + R * decltype(i)::value) % L]; });
+      dft<M, DIR>(s[r]);
+    });
+    static_for<0, M>([&](auto k2) {
+      float2 t[R];
+      static_for<0, R>([&](auto r) { t[r] = s[r][k2]; });
+      dft<R, DIR>(t);
+      static_for<0, R>([&](auto k1) {
+        x[(M * Mi * decltype(k1)::value + R * Ri * decltype(k2)::value) % L] = t[k1];
+      });
+    });
   } else {
     static_assert(L % 2 == 0 || L % 3 == 0 || L % 5 == 0, "radix 2/3/5 lengths only");
     constexpr int R = first_radix<L>();

@@ -74,6 +74,27 @@ struct Group {
   }
 };
 
+// r + sum over the cells marked in c (bit b: the cell whose opposite corner is d_(b+1))
+// of (ph - d), written as r + W ph - sum w_b d_b with W the number of marked cells
+// (five FMAs per component)
+__device__ __forceinline__ float2 outside_sum(float2 r, float2 ph, float2 d1, float2 d2, float2 d3, float2 d4,
+                                             uint32_t c) {
+  const float w1 = float(c & 1u), w2 = float((c >> 1) & 1u);
+  const float w3 = float((c >> 2) & 1u), w4 = float((c >> 3) & 1u);
+  const float W = float(__builtin_popcount(c & 15u));
+  r.x = fmaf(W, ph.x, r.x);
+  r.y = fmaf(W, ph.y, r.y);
+  r.x = fmaf(-w1, d1.x, r.x);
+  r.y = fmaf(-w1, d1.y, r.y);
+  r.x = fmaf(-w2, d2.x, r.x);
+  r.y = fmaf(-w2, d2.y, r.y);
+  r.x = fmaf(-w3, d3.x, r.x);
+  r.y = fmaf(-w3, d3.y, r.y);
+  r.x = fmaf(-w4, d4.x, r.x);
+  r.y = fmaf(-w4, d4.y, r.y);
+  return r;
+}
+
 // c ? a : b on the bit patterns: exact, and both operands are always computed, so
 // the compiler cannot sink the loads feeding one side into a branch
 __device__ __forceinline__ float select_bits(bool c, float a, float b) {
@@ -228,9 +249,6 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
       const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
       const uint32_t c = code_of(k);
-      const float w1 = float(c & 1u), w2 = float((c >> 1) & 1u);
-      const float w3 = float((c >> 2) & 1u), w4 = float((c >> 3) & 1u);
-      const float2 ph = x[k];
       float2 r;
       if constexpr (C::F0_IN_LDS) {
         const float2 fv = f0rows[f0row + k];  // clamped address: always a valid read
@@ -238,15 +256,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       } else {
         r = f0[k];
       }
-      r.x = fmaf(w1, ph.x - d1.x, r.x);
-      r.y = fmaf(w1, ph.y - d1.y, r.y);
-      r.x = fmaf(w2, ph.x - d2.x, r.x);
-      r.y = fmaf(w2, ph.y - d2.y, r.y);
-      r.x = fmaf(w3, ph.x - d3.x, r.x);
-      r.y = fmaf(w3, ph.y - d3.y, r.y);
-      r.x = fmaf(w4, ph.x - d4.x, r.x);
-      r.y = fmaf(w4, ph.y - d4.y, r.y);
-      x[k] = r;
+      x[k] = outside_sum(r, x[k], d1, d2, d3, d4, c);
       // bound the neighbour reads in flight (4 per node)
       if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
@@ -325,17 +335,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         } else {
           r = f0[k];
         }
-        const float w1 = float(c4 & 1u), w2 = float((c4 >> 1) & 1u);
-        const float w3 = float((c4 >> 2) & 1u), w4 = float((c4 >> 3) & 1u);
-        r.x = fmaf(w1, ph.x - d1.x, r.x);
-        r.y = fmaf(w1, ph.y - d1.y, r.y);
-        r.x = fmaf(w2, ph.x - d2.x, r.x);
-        r.y = fmaf(w2, ph.y - d2.y, r.y);
-        r.x = fmaf(w3, ph.x - d3.x, r.x);
-        r.y = fmaf(w3, ph.y - d3.y, r.y);
-        r.x = fmaf(w4, ph.x - d4.x, r.x);
-        r.y = fmaf(w4, ph.y - d4.y, r.y);
-        x[k] = r;
+        x[k] = outside_sum(r, ph, d1, d2, d3, d4, c4);
       }
       if constexpr (EY_IN_F0 && C::F0_IN_LDS) {
         if (in_rows) f0rows[f0row + k] = ey;  // after this thread's last read of the slot
