@@ -40,13 +40,18 @@
 #define FWR_ONCHIP_MIN_WAVES 2
 #endif
 
+// LDS row pitch = N + FWR_ONCHIP_PITCH_PAD complex elements
+#ifndef FWR_ONCHIP_PITCH_PAD
+#define FWR_ONCHIP_PITCH_PAD 1
+#endif
+
 namespace fwr {
 
 template <int N>
 struct Onchip {
   static constexpr int T = N / 4;
   static constexpr int THREADS = 4 * N;
-  static constexpr int PITCH = N + 1;     // complex elements per LDS row
+  static constexpr int PITCH = N + FWR_ONCHIP_PITCH_PAD;  // complex elements per LDS row
   static constexpr int TILE = N * PITCH;  // complex elements
   // N <= 80: the per-node forcing F0 of the n+1 window rows lives in LDS (dynamic,
   // (n+1) * N complex) so that two workgroups share a CU; N = 128 keeps it in
