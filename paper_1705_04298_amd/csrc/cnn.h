@@ -16,6 +16,7 @@ constexpr int kCinS[kLayers] = {8, 32, 32, 32, 32, 32, 32};
 constexpr int kCoutS[kLayers] = {32, 32, 32, 32, 32, 32, 16};
 constexpr int kpad_of(int cin_s) { return ((9 * cin_s + 31) / 32) * 32; }
 
+hipError_t conv_prepare(int N);  // once per grid size, before the first conv / conv_bwd_data
 hipError_t conv(int layer, const uint16_t *x, const uint16_t *wt, const float *bias, void *out, int B, int N,
                 float out_scale, hipStream_t s);
 hipError_t conv_bwd_data(int layer, const uint16_t *dz, const uint16_t *wtb, const uint16_t *act_prev, uint16_t *dx,

@@ -14,6 +14,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "cnn.h"
 
@@ -22,6 +25,8 @@ namespace cnn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -39,67 +44,156 @@ __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, ma
 template <int CIN>
 constexpr int kpad() { return ((9 * CIN + 31) / 32) * 32; }
 
+#ifndef FWR_CNN_TILE_ROWS
+#define FWR_CNN_TILE_ROWS 4
+#endif
+constexpr int kTileRows = FWR_CNN_TILE_ROWS;  // output rows per workgroup of the convolution
+
 // ------------------------------------------------------------------ forward / backward-data
+// One workgroup = kTileRows output rows of one frame.  The (kTileRows + 2) x (N + 2) input
+// halo (zeros outside the frame) is staged once in LDS, so every input pixel is fetched from
+// memory once per tile instead of once per tap; pixel vectors are padded by 8 bf16 so that
+// the 16 pixels of an A operand fall on different LDS banks.  The weights (B operands) stay
+// in registers; each wave takes every 4th 16-pixel M tile of the workgroup.
 // MODE 0: y = relu(conv + bias) -> bf16 NHWC [.., 32]
 // MODE 1: y = (conv + bias) * out_scale for channels 0, 1 -> fp32 planar [B][2][N][N]
 // MODE 2: y = conv * (act[p][c] > 0) -> bf16 NHWC [.., COUT] (gradient through the ReLU)
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ x, const uint16_t *__restrict__ wt,
                                                    const float *__restrict__ bias, void *out,
-                                                   const uint16_t *__restrict__ act, int npix, int N,
+                                                   const uint16_t *__restrict__ act, int N, int ntiles,
                                                    float out_scale) {
-  constexpr int K = kpad<CIN>(), KCH = K / 32, NT = COUT / 16;
+  // C^T = W^T X^T per 16-pixel tile: A = weights (16 output channels x 32 k), B = activations
+  // (32 k x 16 pixels), so lane l ends with channels 4 (l / 16) .. + 3 of pixel l % 16.
+  // Persistent: the weights are loaded once; the workgroup walks the row tiles
+  // blockIdx.x, blockIdx.x + gridDim.x, ...
+  constexpr int K = kpad<CIN>(), KCH = K / 32, MT = COUT / 16, CP = CIN + 8, CH = CIN / 8;
+  constexpr int PIX_STEP = 256 / CH;  // halo pixels staged per pass of the workgroup
+  extern __shared__ __attribute__((aligned(16))) uint16_t halo[];  // [kTileRows + 2][N + 2][CP]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int base = (blockIdx.x * 4 + wave) * 64;  // 64 pixels per wave; N*N is a multiple of 64
-  if (base >= npix) return;
   const int col = lane & 15, kq = lane >> 4;
-  bf16x8 bw[KCH][NT];
+  bf16x8 aw[KCH][MT];
 #pragma unroll
   for (int kc = 0; kc < KCH; ++kc)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) bw[kc][nt] = load8(wt + (size_t)(nt * 16 + col) * K + kc * 32 + 8 * kq);
-  const int NN = N * N;
+    for (int mt = 0; mt < MT; ++mt) aw[kc][mt] = load8(wt + (size_t)(mt * 16 + col) * K + kc * 32 + 8 * kq);
+  float bv[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bv[mt][i] = MODE == 2 ? 0.f : bias[mt * 16 + 4 * kq + i];
+  const int tiles = (N + kTileRows - 1) / kTileRows;
+  const int W = N + 2, hpix = (kTileRows + 2) * W;
+  const size_t NN = (size_t)N * N;
+  const int c8 = threadIdx.x % CH;
 #pragma unroll 1
-  for (int mt = 0; mt < 4; ++mt) {
-    const int p = base + mt * 16 + col;  // A row of this lane
-    const int f = p / NN, rem = p - f * NN, y = rem / N, xx = rem - y * N;
-    f32x4 acc[NT];
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int f = tile / tiles;
+    const int y0 = (tile - f * tiles) * kTileRows;
+    const int rows = N - y0 < kTileRows ? N - y0 : kTileRows;
+    const uint16_t *xf = x + (size_t)f * NN * CIN;
+    __syncthreads();  // the previous tile's LDS reads are done
+    // halo pixel q = (r, xx + 1): walk q = threadIdx.x / CH + PIX_STEP * u, loads first, then stores
+    {
+      int q = threadIdx.x / CH, r = 0, xc = q;
+      while (xc >= W) {
+        xc -= W;
+        ++r;
+      }
+      constexpr int BATCH = 8;
+      for (; q < hpix; ) {
+        uint4 v[BATCH];
+        int qs[BATCH];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < KCH; ++kc) {
-      const int k0 = kc * 32 + 8 * kq;
-      const int t = k0 / CIN, c0 = k0 - t * CIN;
-      const int yy = y + t / 3 - 1, xs = xx + t % 3 - 1;
-      bf16x8 a = zero8();
-      if (t < 9 && yy >= 0 && yy < N && xs >= 0 && xs < N)
-        a = load8(x + ((size_t)f * NN + (size_t)yy * N + xs) * CIN + c0);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[kc][nt], acc[nt], 0, 0, 0);
-    }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int c = nt * 16 + col;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = base + mt * 16 + 4 * kq + i;  // output pixel of acc[nt][i]
-        float v = acc[nt][i];
-        if constexpr (MODE == 0) {
-          v = fmaxf(v + bias[c], 0.f);
-          static_cast<uint16_t *>(out)[(size_t)q * COUT + c] = f2bf(v);
-        } else if constexpr (MODE == 1) {
-          if (c < 2) {
-            const int fq = q / NN, rq = q - fq * NN;
-            static_cast<float *>(out)[((size_t)fq * 2 + c) * NN + rq] = (v + bias[c]) * out_scale;
+        for (int u = 0; u < BATCH; ++u) {
+          const int yy = y0 + r - 1, xx = xc - 1;
+          qs[u] = q;
+          v[u] = make_uint4(0u, 0u, 0u, 0u);
+          if (q < hpix && yy >= 0 && yy < N && xx >= 0 && xx < N)
+            v[u] = *reinterpret_cast<const uint4 *>(xf + ((size_t)yy * N + xx) * CIN + 8 * c8);
+          q += PIX_STEP;
+          xc += PIX_STEP;
+          while (xc >= W) {
+            xc -= W;
+            ++r;
           }
-        } else {
-          const float g = bf2f(act[(size_t)q * COUT + c]) > 0.f ? v : 0.f;
-          static_cast<uint16_t *>(out)[(size_t)q * COUT + c] = f2bf(g);
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+          if (qs[u] < hpix) *reinterpret_cast<uint4 *>(halo + (size_t)qs[u] * CP + 8 * c8) = v[u];
+      }
+    }
+    __syncthreads();
+    const int npix = rows * N;  // output pixels of the tile
+    const size_t gbase = (size_t)f * NN + (size_t)y0 * N;
+    int r0 = 0, x0 = wave * 16;  // (row, column) of the first pixel of tile pt, pt = wave, wave + 4, ...
+    while (x0 >= N) {
+      x0 -= N;
+      ++r0;
+    }
+#pragma unroll 1
+    for (int pt = wave; pt * 16 < npix; pt += 4) {
+      const int pl = pt * 16 + col;  // this lane's pixel (B column, C column)
+      int r = r0, xx = x0 + col;     // 16 <= N: at most one wrap within a tile
+      if (xx >= N) {
+        xx -= N;
+        ++r;
+      }
+      if (pl >= npix) {  // past the tile: a valid LDS read, result discarded
+        r = rows - 1;
+        xx = N - 1;
+      }
+      x0 += 64;  // next tile of this wave: 64 pixels on
+      while (x0 >= N) {
+        x0 -= N;
+        ++r0;
+      }
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < KCH; ++kc) {
+        const int k0 = kc * 32 + 8 * kq;
+        const int t = k0 / CIN, c0 = k0 - t * CIN;
+        bf16x8 b = zero8();
+        if (t < 9) b = *reinterpret_cast<const bf16x8 *>(halo + ((size_t)(r + t / 3) * W + xx + t % 3) * CP + c0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[kc][mt], b, acc[mt], 0, 0, 0);
+      }
+      if (pl >= npix) continue;
+      const size_t q = gbase + pl;
+      if constexpr (MODE == 1) {
+        if (kq == 0) {  // channels 0, 1 of this pixel
+          const size_t fq = q / NN, rq = q - fq * NN;
+          float *o = static_cast<float *>(out);
+          o[(fq * 2 + 0) * NN + rq] = (acc[0][0] + bv[0][0]) * out_scale;
+          o[(fq * 2 + 1) * NN + rq] = (acc[0][1] + bv[0][1]) * out_scale;
+        }
+      } else {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int c = mt * 16 + 4 * kq;  // first of the lane's four channels
+          f32x2 v01, v23;
+          if constexpr (MODE == 0) {
+            v01 = f32x2{fmaxf(acc[mt][0] + bv[mt][0], 0.f), fmaxf(acc[mt][1] + bv[mt][1], 0.f)};
+            v23 = f32x2{fmaxf(acc[mt][2] + bv[mt][2], 0.f), fmaxf(acc[mt][3] + bv[mt][3], 0.f)};
+          } else {
+            const uint2 m = *reinterpret_cast<const uint2 *>(act + q * COUT + c);
+            v01 = f32x2{bf2f(uint16_t(m.x)) > 0.f ? acc[mt][0] : 0.f, bf2f(uint16_t(m.x >> 16)) > 0.f ? acc[mt][1] : 0.f};
+            v23 = f32x2{bf2f(uint16_t(m.y)) > 0.f ? acc[mt][2] : 0.f, bf2f(uint16_t(m.y >> 16)) > 0.f ? acc[mt][3] : 0.f};
+          }
+          const uint2 packed = make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(v01, bf16x2)),
+                                          __builtin_bit_cast(uint32_t, __builtin_convertvector(v23, bf16x2)));
+          *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(out) + q * COUT + c) = packed;
         }
       }
     }
   }
 }
+
+template <int CIN>
+constexpr size_t halo_bytes(int N) { return size_t(kTileRows + 2) * (N + 2) * (CIN + 8) * 2; }
 
 // ------------------------------------------------------------------ weight gradient
 // dW[co][t*CIN + ci] += sum_p dz[p][co] x[p + off(t)][ci]; one block per frame, 32-pixel chunks.
@@ -254,28 +348,94 @@ __global__ void pack_kernel(const float *__restrict__ w, uint16_t *__restrict__ 
 namespace cnn_launch {
 using namespace cnn;
 
+static int tiles_of(int B, int N) { return B * ((N + kTileRows - 1) / kTileRows); }
+
+// persistent grid: as many workgroups as the CUs hold at once (occupancy of the kernel with
+// its dynamic LDS), capped by the number of tiles; measured once per kernel and grid size in
+// conv_prepare, so that launches make no device queries (they may be captured in a graph)
+static std::mutex g_grid_mu;
+static std::map<std::pair<const void *, int>, int> g_resident;  // (kernel, N) -> workgroups
+
+template <typename K>
+static hipError_t measure_grid(K kernel, size_t lds, int N) {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_grid_mu);
+  g_resident[{reinterpret_cast<const void *>(kernel), N}] = (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
+  return hipSuccess;
+}
+
+template <typename K>
+static int grid_of(K kernel, int N, int ntiles) {
+  int g = 256;
+  {
+    std::lock_guard<std::mutex> lock(g_grid_mu);
+    auto it = g_resident.find({reinterpret_cast<const void *>(kernel), N});
+    if (it != g_resident.end()) g = it->second;
+  }
+  return ntiles < g ? ntiles : g;
+}
+
+hipError_t conv_prepare(int N) {
+  // the halo tile can exceed the default 64 KiB of dynamic LDS
+  const void *fns[5] = {reinterpret_cast<const void *>(&conv_kernel<8, 32, 0>),
+                        reinterpret_cast<const void *>(&conv_kernel<32, 32, 0>),
+                        reinterpret_cast<const void *>(&conv_kernel<32, 16, 1>),
+                        reinterpret_cast<const void *>(&conv_kernel<16, 32, 2>),
+                        reinterpret_cast<const void *>(&conv_kernel<32, 32, 2>)};
+  const size_t bytes[5] = {halo_bytes<8>(N), halo_bytes<32>(N), halo_bytes<32>(N), halo_bytes<16>(N),
+                           halo_bytes<32>(N)};
+  for (int i = 0; i < 5; ++i) {
+    if (bytes[i] > 160 * 1024) return hipErrorInvalidValue;
+    const hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes[i]));
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = measure_grid(conv_kernel<8, 32, 0>, bytes[0], N);
+  if (e == hipSuccess) e = measure_grid(conv_kernel<32, 32, 0>, bytes[1], N);
+  if (e == hipSuccess) e = measure_grid(conv_kernel<32, 16, 1>, bytes[2], N);
+  if (e == hipSuccess) e = measure_grid(conv_kernel<16, 32, 2>, bytes[3], N);
+  if (e == hipSuccess) e = measure_grid(conv_kernel<32, 32, 2>, bytes[4], N);
+  return e;
+}
+
 hipError_t conv(int layer, const uint16_t *x, const uint16_t *wt, const float *bias, void *out, int B, int N,
                 float out_scale, hipStream_t s) {
-  const int npix = B * N * N;
-  const dim3 grid((npix + 255) / 256), blk(256);
-  if (layer == 0)
-    hipLaunchKernelGGL((conv_kernel<8, 32, 0>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, 1.f);
-  else if (layer < 6)
-    hipLaunchKernelGGL((conv_kernel<32, 32, 0>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, 1.f);
-  else
-    hipLaunchKernelGGL((conv_kernel<32, 16, 1>), grid, blk, 0, s, x, wt, bias, out, nullptr, npix, N, out_scale);
+  const int nt = tiles_of(B, N);
+  const dim3 blk(256);
+  if (layer == 0) {
+    const auto k = conv_kernel<8, 32, 0>;
+    hipLaunchKernelGGL(k, dim3(grid_of(k, N, nt)), blk, halo_bytes<8>(N), s, x, wt, bias, out,
+                       nullptr, N, nt, 1.f);
+  } else if (layer < 6) {
+    const auto k = conv_kernel<32, 32, 0>;
+    hipLaunchKernelGGL(k, dim3(grid_of(k, N, nt)), blk, halo_bytes<32>(N), s, x, wt, bias, out,
+                       nullptr, N, nt, 1.f);
+  } else {
+    const auto k = conv_kernel<32, 16, 1>;
+    hipLaunchKernelGGL(k, dim3(grid_of(k, N, nt)), blk, halo_bytes<32>(N), s, x, wt, bias, out,
+                       nullptr, N, nt, out_scale);
+  }
   return hipGetLastError();
 }
 
 // gradient w.r.t. the input of `layer` (layer >= 1), masked by the previous layer's ReLU
 hipError_t conv_bwd_data(int layer, const uint16_t *dz, const uint16_t *wtb, const uint16_t *act_prev, uint16_t *dx,
                          int B, int N, hipStream_t s) {
-  const int npix = B * N * N;
-  const dim3 grid((npix + 255) / 256), blk(256);
-  if (layer == 6)
-    hipLaunchKernelGGL((conv_kernel<16, 32, 2>), grid, blk, 0, s, dz, wtb, nullptr, dx, act_prev, npix, N, 1.f);
-  else
-    hipLaunchKernelGGL((conv_kernel<32, 32, 2>), grid, blk, 0, s, dz, wtb, nullptr, dx, act_prev, npix, N, 1.f);
+  const int nt = tiles_of(B, N);
+  const dim3 blk(256);
+  if (layer == 6) {
+    const auto k = conv_kernel<16, 32, 2>;
+    hipLaunchKernelGGL(k, dim3(grid_of(k, N, nt)), blk, halo_bytes<16>(N), s, dz, wtb, nullptr, dx,
+                       act_prev, N, nt, 1.f);
+  } else {
+    const auto k = conv_kernel<32, 32, 2>;
+    hipLaunchKernelGGL(k, dim3(grid_of(k, N, nt)), blk, halo_bytes<32>(N), s, dz, wtb, nullptr, dx,
+                       act_prev, N, nt, 1.f);
+  }
   return hipGetLastError();
 }
 

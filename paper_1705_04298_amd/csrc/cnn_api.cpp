@@ -71,7 +71,8 @@ fwr_status fwr_cnn_create(int32_t n_sub, int32_t n_grid, const uint8_t *mask, in
   if (mask == nullptr || n_sub < 1 || n_grid <= n_sub || (n_grid - n_sub) % 2 || max_batch < 1 ||
       !(input_scale > 0.f))
     return FWR_E_INVAL;
-  if ((n_grid * n_grid) % 64 != 0) return FWR_E_UNSUPPORTED;
+  if ((n_grid * n_grid) % 64 != 0 || n_grid < 16) return FWR_E_UNSUPPORTED;
+  if (conv_prepare(n_grid) != hipSuccess) return FWR_E_UNSUPPORTED;
   auto *c = new (std::nothrow) fwr_cnn_s();
   if (c == nullptr) return FWR_E_NOMEM;
   c->n = n_sub;
