@@ -65,6 +65,18 @@ def pupil_mask(n: int, supersample: int = 16, obstruction_pct: int = 14) -> np.n
     return (2 * count > S * S).astype(np.uint8)
 
 
+def pupil_nodes(mask: np.ndarray) -> np.ndarray:
+    """Fried nodes of the valid subapertures: ``bool[n+1, n+1]``, True at every corner of a
+    valid subaperture (the phase points a reconstruction is judged on)."""
+    m = np.asarray(mask).astype(bool)
+    n = m.shape[0]
+    nodes = np.zeros((n + 1, n + 1), dtype=bool)
+    for a in (0, 1):
+        for b in (0, 1):
+            nodes[a:a + n, b:b + n] |= m
+    return nodes
+
+
 def von_karman_psd(kappa2: np.ndarray, r0: float, L0: float) -> np.ndarray:
     """Von Karman phase PSD [rad^2 m^2] at squared spatial frequency ``kappa2`` [m^-2]."""
     return _VK_CONST * r0 ** (-5.0 / 3.0) * (kappa2 + 1.0 / (L0 * L0)) ** (-11.0 / 6.0)

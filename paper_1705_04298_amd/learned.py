@@ -147,12 +147,7 @@ class LearnedReconstructor:
 
 
 def _pupil_nodes():
-    m = I.pupil_mask(N_SUB).astype(bool)
-    nodes = np.zeros((N_SUB + 1, N_SUB + 1), dtype=bool)
-    for a in (0, 1):
-        for b in (0, 1):
-            nodes[a:a + N_SUB, b:b + N_SUB] |= m
-    return nodes
+    return I.pupil_nodes(I.pupil_mask(N_SUB))
 
 
 def evaluate(params: np.ndarray, frames: int = 4096, seed: int = 99, log=print, steps: int = 20):
