@@ -94,8 +94,11 @@ __device__ __forceinline__ void measured(const MPArgs &a, int pair, int cm, int 
 // mode 0: q2 = F0 (start of the loop; also stores F0 rows of the window)
 // mode 1: q2 = F0 + sum over out-of-pupil cells of (phi - phi_diagonal)
 __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
-  __shared__ float2 ph[(R + 2) * NN];  // phi rows m0-1 .. m0+16
-  __shared__ float2 L[R * LP];
+  // phi rows m0-1 .. m0+16; once the stencil has read them, the same LDS holds the 16
+  // padded lines of the row transforms (R * LP <= (R + 2) * NN), so four blocks fit a CU
+  __shared__ float2 ph[(R + 2) * NN];
+  static_assert(R * LP <= (R + 2) * NN, "line buffer must fit in the phi rows");
+  float2 *const L = ph;
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl;
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
   __syncthreads();
   const bool win_row = m >= a.o && m <= a.o + a.n;
   float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
-#pragma unroll 4
+  float2 fq[R];
+#pragma unroll
   for (int q = 0; q < R; ++q) {
     const int nn = r + R * q;
     float2 f = make_float2(0.f, 0.f);
@@ -136,8 +140,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
       if (c & 4) f = cadd(f, csub(p0, d3));
       if (c & 8) f = cadd(f, csub(p0, d4));
     }
-    L[rl * LP + pad(nn)] = f;
+    fq[q] = f;
   }
+  __syncthreads();  // every stencil read of the phi rows is done
+#pragma unroll
+  for (int q = 0; q < R; ++q) L[rl * LP + pad(r + R * q)] = fq[q];
   __syncthreads();
   fft_stage_a<-1>(L + rl * LP, r, tw);
   __syncthreads();
