@@ -87,9 +87,12 @@ typedef struct {
 
 /* Create a plan: validates the parameters, builds the filter, twiddle and
  * geometry tables in double precision on the host, rounds them to float and
- * uploads them.  Grid sizes handled on-chip: N = 4 * t with
- * t in {2,3,4,5,6,8,10,12,16,20,32} (N = 8 ... 128).  On success *out holds
- * the plan; on failure *out is set to NULL. */
+ * uploads them.  Grid sizes: N = 4 * t with t in {2,3,4,5,6,8,10,12,16,20,32}
+ * (N = 8 ... 128) run on-chip (one LDS tile per frame pair); N = 256 runs as
+ * grid-wide passes through a plan-owned device workspace (start values, the
+ * residual and the group launch of several plans are on-chip only).  Other N
+ * give FWR_E_UNSUPPORTED.  On success *out holds the plan; on failure *out is
+ * set to NULL. */
 fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out);
 
 /* Algorithm 1 (steps 1-4 n_iter times, then step 5 if periodic) for B frames.
@@ -127,7 +130,7 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group);
 
 /* Launch shape of the reconstruction kernel, for reporting: threads per
- * workgroup, frames per workgroup, dynamic LDS bytes per workgroup. */
+ * workgroup, frames per workgroup, LDS bytes per workgroup (static + dynamic). */
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes);
 
@@ -155,7 +158,8 @@ fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const f
  * branches when `stream` is being captured into a HIP graph).  Each item is as
  * fwr_reconstruct (d_start / d_resid optional, as fwr_reconstruct_start).  A
  * plan may appear in one item only (its workspace serves one batch at a time);
- * one call at a time per process.
+ * one call at a time per process.  The first call creates the streams and
+ * events (on the current device); make one call before capturing a graph.
  */
 typedef struct {
   fwr_plan_t plan;
@@ -205,8 +209,8 @@ fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, ui
  */
 typedef struct fwr_cnn_s *fwr_cnn_t;
 
-/* mask: HOST n*n valid-subaperture bytes (as for fwr_plan); N*N must be a
- * multiple of 64.  training = 0 keeps two activation buffers (inference);
+/* mask: HOST n*n valid-subaperture bytes (as for fwr_plan); N >= 16 and N*N a
+ * multiple of 64 (FWR_E_UNSUPPORTED otherwise).  training = 0 keeps two activation buffers (inference);
  * training = 1 keeps every layer's activations and gradient buffers.  Weights
  * start at zero: call fwr_cnn_set_params. */
 fwr_status fwr_cnn_create(int32_t n_sub, int32_t n_grid, const uint8_t *mask, int32_t max_batch, float input_scale,
@@ -214,7 +218,8 @@ fwr_status fwr_cnn_create(int32_t n_sub, int32_t n_grid, const uint8_t *mask, in
 /* HOST parameter arrays of `count` = 47714 floats. set resets the Adam state. */
 fwr_status fwr_cnn_set_params(fwr_cnn_t cnn, const float *h_params, int32_t count);
 fwr_status fwr_cnn_get_params(fwr_cnn_t cnn, float *h_params, int32_t count);
-/* d_slopes: float[B][2][n][n]; d_pred: float[B][2][N][N] predicted slopes. */
+/* d_slopes: float[B][2][n][n]; d_pred: float[B][2][N][N] predicted slopes.
+ * Enqueues kernels only (may be captured in a HIP graph). */
 fwr_status fwr_cnn_forward(fwr_cnn_t cnn, const float *d_slopes, float *d_pred, int32_t B);
 /* After fwr_cnn_forward on the same batch (training mode): loss = mean over the
  * out-of-pupil cells of both channels of (scaled prediction - scaled target)^2,

@@ -1,11 +1,11 @@
 // On-chip Gerchberg extension + Fourier reconstruction for padded grids N <= 128.
 //
-// One workgroup takes TWO frames.  Everything the loop iterates on is real,
-// and every Fourier-domain operator in it is real and even, so the two frames
+// Frames go in pairs.  Everything the loop iterates on is real, and every
+// Fourier-domain operator in it is real and even, so the two frames of a pair
 // ride in one complex field (frame A = real part, frame B = imaginary part)
 // and share every FFT.  Per frame pair the loop state lives in registers and
 // one N x N complex LDS tile; HBM is touched only to read the slopes and to
-// write the result.
+// write the result.  A workgroup takes PAIRS pairs (see Group below).
 //
 // Formulation (Fried model; exact rewrite of Algorithm 1 steps 1-4):
 //   Step 2 of each iteration, phi~ = (G_x* S_x + G_y* S_y) / |G|^2 followed
@@ -22,7 +22,7 @@
 //   The final reconstruction (Eq. 2 with the Eq. 3 filter) is the same
 //   Fourier step with 1 / (|G|^2 + gamma W_eta/W_phi).
 //
-// Thread layout: 4 lanes per grid line (see fft_lane.h), 4N threads.
+// Thread layout: 4 lanes per grid line (see fft_lane.h), 4N threads per pair.
 //   row phase    : thread (line = m, lane j) holds nodes (m, 4k + j), k < T
 //   column phase : thread (line = c, lane j) holds rows 4k + j of LDS column c
 // LDS tile: N rows x PITCH complex.  In the row phase a thread's k-th value
@@ -34,8 +34,9 @@
 
 #include <cstdint>
 
-// Minimum waves per SIMD the register allocation must allow for N <= 80 (2: one
-// workgroup of 5 waves per CU, up to 256 VGPRs; 3: two workgroups, <= 168 VGPRs).
+// Minimum waves per SIMD the register allocation must allow for N <= 80 and one
+// pair per workgroup (2: up to 256 VGPRs; 3: <= 168 VGPRs); larger groups raise it
+// to what their waves need (Group::WAVES_PER_SIMD).
 #ifndef FWR_ONCHIP_MIN_WAVES
 #define FWR_ONCHIP_MIN_WAVES 2
 #endif
@@ -54,8 +55,8 @@ struct Onchip {
   static constexpr int PITCH = N + FWR_ONCHIP_PITCH_PAD;  // complex elements per LDS row
   static constexpr int TILE = N * PITCH;  // complex elements
   // N <= 80: the per-node forcing F0 of the n+1 window rows lives in LDS (dynamic,
-  // (n+1) * N complex) so that two workgroups share a CU; N = 128 keeps it in
-  // registers (one workgroup per CU).
+  // (n+1) * PITCH complex per pair), which leaves registers for two pairs per CU;
+  // N = 128 keeps it in registers (one pair per CU: its tile alone is 132 KB).
   static constexpr bool F0_IN_LDS = N <= 80;
   static constexpr int WAVES_PER_SIMD = N <= 80 ? FWR_ONCHIP_MIN_WAVES : 2;
   // residual partials per frame pair: one set per wave (full waves) or per thread
