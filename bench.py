@@ -84,11 +84,17 @@ def cpu_baseline(slopes: np.ndarray, workers: int, sample: int):
 
 
 def kernel_fingerprint() -> str:
+    """Hash of the kernel sources without comments and blank lines (a comment edit does not
+    change the kernel the profile measured)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1705_04298_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1705_04298_amd", "csrc", name)) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
