@@ -58,7 +58,13 @@ typedef enum {
 } fwr_status;
 
 typedef enum {
-  FWR_MODEL_FRIED = 0      /* Fried-geometry Shack-Hartmann slopes */
+  FWR_MODEL_FRIED = 0,     /* Fried-geometry Shack-Hartmann slopes */
+  FWR_MODEL_SINC = 1       /* lenslet-averaging model of Eq. 4: a subaperture measures the
+                              difference of the phase averaged over its opposite edges;
+                              transfer function exp(i pi (k'+l')/N) 2i sin(pi k'/N) sinc(l'/N)
+                              (x; y transposed), signed frequencies, zero on the Nyquist row
+                              and column.  Grids N = 8, 16, 24, 32, 40, 48, 64, 80; no per-
+                              iteration Eq. 5, start values, residual or device generator. */
 } fwr_model;
 
 typedef struct fwr_plan_s *fwr_plan_t;   /* opaque; owns every device table */
@@ -118,6 +124,7 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream);
 /* Launch shape of the on-chip kernel (grids up to 128 x 128): frames per
  * workgroup, 2 (one frame pair) or 4, 8, 16 where the kernel is built for it and the
  * workgroup's LDS fits (FWR_E_UNSUPPORTED otherwise; FWR_E_INVAL for odd or < 2).
+ * Plans of FWR_MODEL_SINC take 1 or 2 frames per workgroup (one frame per complex field).
  * Results do not depend on it.  Plans start from the choice autotuned earlier in the
  * process for the same device, N, n, n_iter and Eq. 5 mode, else from a rule that
  * balances the waves of a workgroup over the four SIMDs of a CU. */

@@ -25,7 +25,8 @@ Fourier domain"):
 * Sec. 4.1 -- zero iterations means the measurement padded with zeros.
 
 Readings where the paper is silent (each listed in the design notes):
-  * G is the Fried model (the paper's own filter is only referenced);
+  * G is the Fried model (the paper's own filter is only referenced), or the
+    lenslet-averaging (sinc) model of Eq. 4 read on the DFT grid (`sinc_model`);
   * the pupil sits centred in the padded grid, offset (N - n) / 2;
   * out-of-pupil start values are zero;
   * Eq. 5 is applied once, after the loop (optionally after every iteration);
@@ -90,6 +91,55 @@ def fried_model(N: int):
     return Gx, Gy
 
 
+def sinc_model(N: int):
+    """Fourier transfer functions of the lenslet-averaging model of Eq. 4 (sinc reading).
+
+    A subaperture measures the difference of the phase averaged over its two opposite
+    edges (Sec. 2, Eq. 4: comb sampling x (box average convolved with the gradient)).
+    For a grid mode exp(2 pi i (k' n + l' m) / N) of the node phase, interpolated as the
+    same continuous mode, the x measurement of cell (m, n) is the node value times
+        G_x = exp(i pi (k' + l') / N) 2i sin(pi k' / N) sinc(l' / N),
+    sinc(u) = sin(pi u) / (pi u), with signed frequencies k', l' in [-N/2, N/2); G_y swaps
+    the roles of k' and l'.  The slopes of a real phase must be real, so the transfer
+    function is the Hermitian part of this expression on the DFT grid; it equals the
+    expression off the Nyquist lines and vanishes on them (even N), where the expression is
+    anti-Hermitian.  The pixel-size correction d - d_px of the paper is not modelled.
+    """
+    l, k = frequency_indices(N)
+    ks = np.where(k < (N + 1) // 2, k, k - N).astype(np.float64)
+    ls = np.where(l < (N + 1) // 2, l, l - N).astype(np.float64)
+    shift = np.exp(1j * np.pi * (ks + ls) / N)
+    Gx = shift * 2j * np.sin(np.pi * ks / N) * np.sinc(ls / N)
+    Gy = shift * 2j * np.sin(np.pi * ls / N) * np.sinc(ks / N)
+    if N % 2 == 0:
+        nyq = (l == N // 2) | (k == N // 2)
+        Gx = np.where(nyq, 0.0, Gx)
+        Gy = np.where(nyq, 0.0, Gy)
+    return Gx, Gy
+
+
+def sinc_singular_set(N: int) -> np.ndarray:
+    """Where the sinc model's |G|^2 vanishes, by index: (0, 0) and, for even N, the Nyquist
+    row and column."""
+    S = np.zeros((N, N), dtype=bool)
+    S[0, 0] = True
+    if N % 2 == 0:
+        S[N // 2, :] = True
+        S[:, N // 2] = True
+    return S
+
+
+def slope_model(name: str, N: int):
+    """(G_x, G_y, singular set) of the named model: "fried" or "sinc"."""
+    if name == "fried":
+        Gx, Gy = fried_model(N)
+        return Gx, Gy, singular_set(N)
+    if name == "sinc":
+        Gx, Gy = sinc_model(N)
+        return Gx, Gy, sinc_singular_set(N)
+    raise ValueError(f"unknown slope model {name!r}")
+
+
 def singular_set(N: int) -> np.ndarray:
     """Boolean N x N map of the frequencies where |G|^2 vanishes for the Fried model.
 
@@ -103,12 +153,12 @@ def singular_set(N: int) -> np.ndarray:
 
 
 def wiener_reconstructor(Gx: np.ndarray, Gy: np.ndarray, gamma: float = 0.0,
-                         ratio: Optional[np.ndarray] = None):
+                         ratio: Optional[np.ndarray] = None, singular: Optional[np.ndarray] = None):
     """Eq. 3: R_{x,y} = G*_{x,y} / (|G_x|^2 + |G_y|^2 + gamma W_eta/W_phi).
 
     ``ratio`` is W_eta / W_phi on the DFT grid (ignored when gamma == 0).
-    Where the denominator is zero by construction (the singular set, with no
-    regularisation) the filter is set to zero.
+    Where the denominator is zero by construction (the singular set of the model,
+    ``singular``, default the Fried one, with no regularisation) the filter is zero.
     """
     N = Gx.shape[0]
     den = np.abs(Gx) ** 2 + np.abs(Gy) ** 2
@@ -118,7 +168,7 @@ def wiener_reconstructor(Gx: np.ndarray, Gy: np.ndarray, gamma: float = 0.0,
         den = den + gamma * ratio
         zero = den == 0.0
     else:
-        zero = singular_set(N)
+        zero = singular_set(N) if singular is None else singular
     safe = np.where(zero, 1.0, den)
     Rx = np.where(zero, 0.0, np.conj(Gx) / safe)
     Ry = np.where(zero, 0.0, np.conj(Gy) / safe)
@@ -268,21 +318,22 @@ class Params(NamedTuple):
     r0: float = 0.15
     L0: float = 25.0
     d: float = 0.2
+    model: str = "fried"   # slope model: "fried" or "sinc"
 
 
 def final_filters(p: Params):
-    Gx, Gy = fried_model(p.n_grid)
+    Gx, Gy, S = slope_model(p.model, p.n_grid)
     ratio = None
     if p.gamma != 0.0:
         ratio = noise_to_signal(p.n_grid, p.d, p.r0, p.L0, p.noise_var)
-    return wiener_reconstructor(Gx, Gy, p.gamma, ratio)
+    return wiener_reconstructor(Gx, Gy, p.gamma, ratio, S)
 
 
 def extend(slopes: np.ndarray, mask: np.ndarray, p: Params, start=None) -> GerchbergResult:
     """Padded measurement -> Algorithm 1 (steps 1-5) -> extended slopes on the N x N grid."""
     s0x, s0y, P = padded_measurement(slopes, mask, p.n_grid)
-    Gx, Gy = fried_model(p.n_grid)
-    Rx, Ry = wiener_reconstructor(Gx, Gy, 0.0)
+    Gx, Gy, S = slope_model(p.model, p.n_grid)
+    Rx, Ry = wiener_reconstructor(Gx, Gy, 0.0, singular=S)
     return gerchberg(s0x, s0y, P, Gx, Gy, Rx, Ry, p.n_iter, p.periodic,
                      p.periodic_each_iter, start)
 

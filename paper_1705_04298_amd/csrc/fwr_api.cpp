@@ -9,10 +9,12 @@
 #include <vector>
 
 #include "../../include/fwr.h"
+#include <complex>
 #include <map>
 #include <mutex>
 #include <tuple>
 
+#include "fourier.h"
 #include "gen.h"
 #include "multipass.h"
 #include "onchip.h"
@@ -42,6 +44,10 @@ struct fwr_plan_s {
   const float2 *tw_lane = nullptr;
   const uint32_t *codes = nullptr;
   int pairs = 1;  // frame pairs per workgroup of the on-chip kernel
+  // Fourier-domain path (slope models without a compact stencil)
+  bool fourier = false;
+  fwr::FourierArgs fa{};
+  int frames = 1;  // frames per workgroup of the Fourier-domain kernel
   // multi-pass path (N = 256)
   bool multipass = false;
   fwr::MPArgs mp{};
@@ -60,16 +66,23 @@ constexpr int kPairsOptions[] = {1, 2, 4, 8};
 struct TuneKey {
   int device, N, n, n_iter;
   bool each;
+  int model;
   bool operator<(const TuneKey &o) const {
-    return std::tie(device, N, n, n_iter, each) < std::tie(o.device, o.N, o.n, o.n_iter, o.each);
+    return std::tie(device, N, n, n_iter, each, model) < std::tie(o.device, o.N, o.n, o.n_iter, o.each, o.model);
   }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tuned;
 
-void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs) {
+void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs, int model = FWR_MODEL_FRIED) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tuned[TuneKey{device, N, n, n_iter, each}] = pairs;
+  g_tuned[TuneKey{device, N, n, n_iter, each, model}] = pairs;
+}
+
+int tuned_value(int device, int N, int n, int n_iter, bool each, int model) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tuned.find(TuneKey{device, N, n, n_iter, each, model});
+  return it == g_tuned.end() ? 0 : it->second;
 }
 
 // The tuned choice when there is one.  Otherwise: two pairs when one pair's waves
@@ -78,11 +91,7 @@ void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs) 
 // 3, 3, 2, 2); one pair elsewhere, where larger groups measured slower (they lower the
 // register budget per wave).
 int tuned_pairs(int device, int N, int n, int n_iter, bool each) {
-  {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tuned.find(TuneKey{device, N, n, n_iter, each});
-    if (it != g_tuned.end()) return it->second;
-  }
+  if (const int v = tuned_value(device, N, n, n_iter, each, FWR_MODEL_FRIED)) return v;
   const int waves = (fwr::onchip_threads(N, 1) + 63) / 64;
   if (waves > 4 && waves % 4 == 1 && fwr::onchip_pairs_ok(N, n, 2, each)) return 2;
   return 1;
@@ -126,6 +135,7 @@ void filter_values(const fwr_params &p, int l, int k, double &hl, double &hf) {
 }
 
 fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out);
+fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out);
 
 }  // namespace
 
@@ -151,6 +161,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const int n = p.n_sub, N = p.n_grid;
   if (n < 1 || N <= n || (N - n) % 2 != 0 || p.mask == nullptr) return FWR_E_INVAL;
   if (p.n_iter < 0 || p.n_iter > 10000 || p.max_batch < 1) return FWR_E_INVAL;
+  if (p.model == FWR_MODEL_SINC) return plan_fourier(p, out);
   if (p.model != FWR_MODEL_FRIED) return FWR_E_UNSUPPORTED;
   if (p.alpha_map == nullptr && p.gamma != 0.0) {
     if (!(p.gamma > 0.0) || !(p.noise_var >= 0.0) || !(p.r0 > 0.0) || !(p.L0 > 0.0) || !(p.d > 0.0))
@@ -266,7 +277,15 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (in == nullptr || out == nullptr) return FWR_E_INVAL;
-  if ((start != nullptr || resid != nullptr) && plan->multipass) return FWR_E_UNSUPPORTED;
+  if ((start != nullptr || resid != nullptr) && (plan->multipass || plan->fourier)) return FWR_E_UNSUPPORTED;
+  if (plan->fourier) {
+    fwr::FourierArgs a = plan->fa;
+    a.slopes = in;
+    a.out = out;
+    a.B = B;
+    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) | (extend ? fwr::kFourierExtend : 0);
+    return fwr::fourier_launch(plan->N, a, st, plan->frames) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  }
   if (start != nullptr && plan->n_iter == 0) return FWR_E_INVAL;
   if (plan->multipass) {
     fwr::MPArgs a = plan->mp;
@@ -349,6 +368,7 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
 fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, uint64_t *d_counter, float r0,
                         float L0, float noise_sigma, float *d_slopes, float *d_phase, int32_t B) {
   if (!valid(plan)) return FWR_E_STATE;
+  if (plan->fourier) return FWR_E_UNSUPPORTED;  // the generator samples Fried slopes
   if (B < 0 || B > plan->max_batch || (first_frame & 1u)) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (d_slopes == nullptr || !(r0 > 0.f) || !(L0 > 0.f) || !(noise_sigma >= 0.f) || !(plan->d > 0.0))
@@ -395,6 +415,12 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
     if (lds_bytes) *lds_bytes = 0;
     return FWR_OK;
   }
+  if (plan->fourier) {
+    if (threads) *threads = fwr::fourier_threads(plan->N, plan->frames);
+    if (frames_per_group) *frames_per_group = plan->frames;
+    if (lds_bytes) *lds_bytes = fwr::fourier_lds_bytes(plan->N, plan->n, plan->frames);
+    return FWR_OK;
+  }
   if (threads) *threads = fwr::onchip_threads(plan->N, plan->pairs);
   if (frames_per_group) *frames_per_group = 2 * plan->pairs;
   if (lds_bytes) *lds_bytes = fwr::onchip_lds_bytes(plan->N, plan->n, plan->pairs);
@@ -404,6 +430,12 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
 fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (plan->multipass) return frames_per_group == 2 ? FWR_OK : FWR_E_UNSUPPORTED;
+  if (plan->fourier) {
+    if (frames_per_group < 1) return FWR_E_INVAL;
+    if (!fwr::fourier_frames_ok(plan->N, plan->n, frames_per_group)) return FWR_E_UNSUPPORTED;
+    plan->frames = frames_per_group;
+    return FWR_OK;
+  }
   if (frames_per_group < 2 || frames_per_group % 2 != 0) return FWR_E_INVAL;
   const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
   if (!fwr::onchip_pairs_ok(plan->N, plan->n, frames_per_group / 2, each)) return FWR_E_UNSUPPORTED;
@@ -420,6 +452,11 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   }
   const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
   const int n = plan->n, N = plan->N;
+  // candidate launch shapes: frame pairs per workgroup (on-chip) or frames (Fourier-domain)
+  int *unit = plan->fourier ? &plan->frames : &plan->pairs;
+  auto shape_ok = [&](int u) {
+    return plan->fourier ? fwr::fourier_frames_ok(N, n, u) : fwr::onchip_pairs_ok(N, n, u, each);
+  };
   // the kernels' work does not depend on the slope values: time them on zeros
   float *d_in = nullptr, *d_out = nullptr;
   const size_t in_bytes = (size_t)B * 2 * n * n * sizeof(float);
@@ -432,13 +469,13 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
             hipMemsetAsync(d_in, 0, in_bytes, plan->stream) == hipSuccess;
-  const int before = plan->pairs;
+  const int before = *unit;
   int best = before;
   float best_ms = 0.f;
   for (int pairs : kPairsOptions) {
     if (!ok) break;
-    if (!fwr::onchip_pairs_ok(N, n, pairs, each)) continue;
-    plan->pairs = pairs;
+    if (!shape_ok(pairs)) continue;
+    *unit = pairs;
     float ms = 0.f;
     ok = run(plan, d_in, d_out, B, false) == FWR_OK && hipEventRecord(e0, plan->stream) == hipSuccess;
     for (int r = 0; r < 3 && ok; ++r) ok = run(plan, d_in, d_out, B, false) == FWR_OK;
@@ -454,10 +491,10 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(d_in);
   (void)hipFree(d_out);
-  plan->pairs = ok ? best : before;
+  *unit = ok ? best : before;
   if (!ok) return FWR_E_DEVICE;
-  remember_pairs(plan->device, N, n, plan->n_iter, each, best);
-  if (frames_per_group) *frames_per_group = 2 * best;
+  remember_pairs(plan->device, N, n, plan->n_iter, each, best, plan->fourier ? FWR_MODEL_SINC : FWR_MODEL_FRIED);
+  if (frames_per_group) *frames_per_group = plan->fourier ? best : 2 * best;
   return FWR_OK;
 }
 
@@ -565,3 +602,138 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
 }
 
 }  // namespace
+
+namespace {
+
+// Lenslet-averaging (sinc) model of Eq. 4 at DFT index (l, k): the Hermitian part of
+// exp(i pi (k' + l') / N) 2i sin(pi k' / N) sinc(l' / N) (x) and its transpose (y), signed
+// k', l'; zero on the Nyquist row and column of an even grid.
+void sinc_g(int l, int k, int N, std::complex<double> &gx, std::complex<double> &gy) {
+  gx = gy = 0.0;
+  if (N % 2 == 0 && (l == N / 2 || k == N / 2)) return;
+  const double ks = k < (N + 1) / 2 ? k : k - N, ls = l < (N + 1) / 2 ? l : l - N;
+  auto sinc = [](double u) { return u == 0.0 ? 1.0 : std::sin(kPi * u) / (kPi * u); };
+  const std::complex<double> shift = std::polar(1.0, kPi * (ks + ls) / N);
+  const std::complex<double> two_i(0.0, 2.0);
+  gx = shift * two_i * std::sin(kPi * ks / N) * sinc(ls / N);
+  gy = shift * two_i * std::sin(kPi * ls / N) * sinc(ks / N);
+}
+
+bool sinc_singular(int l, int k, int N) {
+  return (l == 0 && k == 0) || (N % 2 == 0 && (l == N / 2 || k == N / 2));
+}
+
+fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
+  const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
+  if (!fwr::fourier_supported(N) || p.periodic_each_iter) return FWR_E_UNSUPPORTED;
+  if (!fwr::fourier_frames_ok(N, n, 1)) return FWR_E_UNSUPPORTED;
+  const int T = N / 4, threads = fwr::fourier_threads(N, 1);
+  static const int beta[4] = {0, 2, 1, 3};
+  const double inv = 1.0 / (double(N) * double(N));
+  std::vector<float> alpha((size_t)T * threads);
+  std::vector<float2> betat((size_t)T * threads), fin_a((size_t)T * threads), fin_b((size_t)T * threads);
+  for (int c = 0; c < N; ++c) {
+    const int kf = (c % T) + T * beta[c / T];  // x-frequency held in LDS column c
+    for (int jj = 0; jj < 4; ++jj) {
+      const size_t base = (size_t)(4 * c + jj) * T;
+      for (int k2 = 0; k2 < T; ++k2) {
+        const int l = k2 + T * beta[jj];      // y-frequency of this slot
+        std::complex<double> gx, gy;
+        sinc_g(l, kf, N, gx, gy);
+        const double g2 = std::norm(gx) + std::norm(gy);
+        double al = 0.0;
+        std::complex<double> be = 0.0, fa = 0.0, fb = 0.0;
+        if (!sinc_singular(l, kf, N)) {
+          const double a = std::norm(gx) / g2, b = std::norm(gy) / g2;
+          const std::complex<double> cc = gx * std::conj(gy) / g2;
+          al = 0.5 * (a + b) + cc.imag();
+          be = std::complex<double>(0.5 * (a - b), cc.real());
+        }
+        const double den = g2 + regulariser(p, l, kf);
+        if (den > 0.0 && !(p.gamma == 0.0 && p.alpha_map == nullptr && sinc_singular(l, kf, N))) {
+          const std::complex<double> rx = std::conj(gx) / den, ry = std::conj(gy) / den;
+          const std::complex<double> I(0.0, 1.0);
+          fa = 0.5 * (rx - I * ry);
+          fb = 0.5 * (rx + I * ry);
+        }
+        alpha[base + k2] = float(al * inv);
+        betat[base + k2] = make_float2(float(be.real() * inv), float(be.imag() * inv));
+        fin_a[base + k2] = make_float2(float(fa.real() * inv), float(fa.imag() * inv));
+        fin_b[base + k2] = make_float2(float(fb.real() * inv), float(fb.imag() * inv));
+      }
+    }
+  }
+  std::vector<float2> tw((size_t)T * 4);
+  for (int k2 = 0; k2 < T; ++k2)
+    for (int jj = 0; jj < 4; ++jj) {
+      const double ang = -2.0 * kPi * double(jj) * double(k2) / double(N);
+      tw[(size_t)k2 * 4 + jj] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
+    }
+  // in-pupil bits: bit k of thread t = 4m + j marks cell (m, 4k + j)
+  std::vector<uint32_t> pup(threads, 0u);
+  for (int m = 0; m < N; ++m)
+    for (int jj = 0; jj < 4; ++jj)
+      for (int k = 0; k < T; ++k) {
+        const int i = m - o, c = 4 * k + jj - o;
+        if (i >= 0 && i < n && c >= 0 && c < n && p.mask[(size_t)i * n + c]) pup[4 * m + jj] |= 1u << k;
+      }
+  auto *plan = new (std::nothrow) fwr_plan_s();
+  if (plan == nullptr) return FWR_E_NOMEM;
+  bool prepared = hipGetDevice(&plan->device) == hipSuccess;
+  for (int frames = 1; frames <= 2 && prepared; ++frames)
+    if (fwr::fourier_frames_ok(N, n, frames)) prepared = fwr::fourier_prepare(N, n, frames) == hipSuccess;
+  if (!prepared) {
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t b_a = alpha.size() * sizeof(float), b_c = betat.size() * sizeof(float2);
+  const size_t b_tw = tw.size() * sizeof(float2), b_p = pup.size() * sizeof(uint32_t);
+  const size_t off_b = b_a, off_fa = off_b + b_c, off_fb = off_fa + b_c, off_tw = off_fb + b_c,
+               off_p = off_tw + b_tw, total = off_p + b_p;
+  char *mem = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&mem), total) != hipSuccess) {
+    delete plan;
+    return FWR_E_NOMEM;
+  }
+  hipError_t e = hipMemcpy(mem, alpha.data(), b_a, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_b, betat.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_fa, fin_a.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_fb, fin_b.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_p, pup.data(), b_p, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  fwr::FourierArgs &a = plan->fa;
+  a.alpha = reinterpret_cast<const float *>(mem);
+  a.beta = reinterpret_cast<const float2 *>(mem + off_b);
+  a.fin_a = reinterpret_cast<const float2 *>(mem + off_fa);
+  a.fin_b = reinterpret_cast<const float2 *>(mem + off_fb);
+  a.tw_lane = reinterpret_cast<const float2 *>(mem + off_tw);
+  a.inpupil = reinterpret_cast<const uint32_t *>(mem + off_p);
+  a.n = n;
+  a.o = o;
+  a.n_iter = p.n_iter;
+  plan->magic = kMagic;
+  plan->n = n;
+  plan->N = N;
+  plan->o = o;
+  plan->n_iter = p.n_iter;
+  plan->flags = p.periodic ? fwr::kFlagPeriodic : 0;
+  plan->max_batch = p.max_batch;
+  plan->stream = static_cast<hipStream_t>(p.stream);
+  plan->d_mem = mem;
+  plan->fourier = true;
+  plan->d = p.d;
+  // tuned earlier in the process, else two frames when one frame's waves number 4k + 1
+  const int tuned = tuned_value(plan->device, N, n, p.n_iter, false, FWR_MODEL_SINC);
+  const int waves = (fwr::fourier_threads(N, 1) + 63) / 64;
+  plan->frames = tuned ? tuned : (waves > 4 && waves % 4 == 1 && fwr::fourier_frames_ok(N, n, 2)) ? 2 : 1;
+  *out = plan;
+  return FWR_OK;
+}
+
+}  // namespace
+

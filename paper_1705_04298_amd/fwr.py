@@ -23,6 +23,8 @@ FWR_E_NOMEM = -3
 FWR_E_DEVICE = -4
 FWR_E_STATE = -5
 FWR_MODEL_FRIED = 0
+FWR_MODEL_SINC = 1
+MODELS = {"fried": FWR_MODEL_FRIED, "sinc": FWR_MODEL_SINC}
 
 # grid sizes handled by the on-chip kernel (N = 4 t)
 ONCHIP_GRIDS = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 128)
@@ -215,7 +217,7 @@ class Plan:
                  periodic_each_iter: bool = False, gamma: float = 1.0, noise_var: float = 0.05 ** 2,
                  r0: float = 0.15, L0: float = 25.0, d: float = 0.2,
                  alpha_map: Optional[np.ndarray] = None, max_batch: int = 4096,
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, model: str = "fried"):
         mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if mask.shape != (n_sub, n_sub):
             raise ValueError(f"mask must be {n_sub}x{n_sub}")
@@ -227,7 +229,10 @@ class Plan:
         p.n_sub, p.n_grid = self.n_sub, self.n_grid
         p.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         p.n_iter, p.periodic, p.periodic_each_iter = int(n_iter), int(bool(periodic)), int(bool(periodic_each_iter))
-        p.model = FWR_MODEL_FRIED
+        if model not in MODELS:
+            raise ValueError(f"model must be one of {sorted(MODELS)}")
+        self.model = model
+        p.model = MODELS[model]
         p.gamma, p.noise_var, p.r0, p.L0, p.d = float(gamma), float(noise_var), float(r0), float(L0), float(d)
         p.alpha_map = (self._alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                        if self._alpha is not None else None)

@@ -112,6 +112,32 @@ def fried_slopes_from_nodes(phi: np.ndarray):
     return sx, sy
 
 
+def sinc_slopes_from_screen(screen: np.ndarray, n: int):
+    """Lenslet-averaged slopes (Eq. 4: the difference of the phase averaged over opposite
+    lenslet edges) of the periodic ``M x M`` screen, for the ``n x n`` lenslets whose corner
+    nodes are screen samples [0, n] x [0, n].
+
+    Computed on the screen's own grid: a screen mode exp(2 pi i (k' x + l' y) / M) (signed
+    k', l') has the x measurement exp(i pi (k' + l') / M) 2i sin(pi k' / M) sinc(l' / M)
+    times its value at the lenslet's first corner, y likewise; Nyquist components, whose
+    measurement of a real screen is not real, are dropped.  Returns (sx, sy), each n x n.
+    """
+    M = screen.shape[0]
+    f = np.fft.fftfreq(M) * M                  # signed integer frequencies
+    fx, fy = np.meshgrid(f, f)                 # fx along columns (x), fy along rows (y)
+    shift = np.exp(1j * np.pi * (fx + fy) / M)
+    hx = shift * 2j * np.sin(np.pi * fx / M) * np.sinc(fy / M)
+    hy = shift * 2j * np.sin(np.pi * fy / M) * np.sinc(fx / M)
+    if M % 2 == 0:
+        nyq = (np.abs(fx) == M // 2) | (np.abs(fy) == M // 2)
+        hx[nyq] = 0.0
+        hy[nyq] = 0.0
+    S = np.fft.fft2(screen)
+    sx = np.real(np.fft.ifft2(hx * S))[:n, :n]
+    sy = np.real(np.fft.ifft2(hy * S))[:n, :n]
+    return sx, sy
+
+
 @dataclasses.dataclass(frozen=True)
 class Workload:
     """Geometry and statistics of one synthetic workload."""
@@ -123,6 +149,7 @@ class Workload:
     noise_sigma: float = 0.05  # slope noise [rad]
     screen_size: int = 256     # M, periodic screen side in samples of pitch d
     config_id: int = 1
+    model: str = "fried"       # slope measurement: "fried" (corner differences) or "sinc" (Eq. 4)
 
     @property
     def d(self) -> float:
@@ -136,6 +163,7 @@ SPHERE_40_BATCH = dataclasses.replace(SPHERE_40, config_id=2)
 ELT_128 = Workload(n_sub=128, diameter=39.0, screen_size=512, config_id=3)
 MIX_24 = Workload(n_sub=24, diameter=8.0, screen_size=256, config_id=5)
 MIX_64 = Workload(n_sub=64, diameter=8.0, screen_size=256, config_id=5)
+SPHERE_40_SINC = Workload(n_sub=40, diameter=8.0, screen_size=256, config_id=6, model="sinc")
 
 
 def frame_rng(config_id: int, index: int) -> np.random.Generator:
@@ -156,7 +184,10 @@ def make_frame(w: Workload, index: int, noise_sigma: Optional[float] = None,
     sig = w.noise_sigma if noise_sigma is None else noise_sigma
     scr = vk_screen(rng, w.screen_size, w.d, r0v, w.L0)
     phi = scr[: n + 1, : n + 1].copy()
-    sx, sy = fried_slopes_from_nodes(phi)
+    if w.model == "sinc":
+        sx, sy = sinc_slopes_from_screen(scr, n)
+    else:
+        sx, sy = fried_slopes_from_nodes(phi)
     noise = rng.standard_normal((2, n, n)) * sig
     m = pupil_mask(n).astype(bool)
     out = np.zeros((2, n, n))

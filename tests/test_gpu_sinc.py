@@ -1,0 +1,106 @@
+"""Lenslet-averaging (sinc) slope model on the Fourier-domain kernel vs the FP64 oracle (needs
+an MI355X).  Same tolerances as the Fried path: phase <= 1e-5 relative rms per frame, extended
+slopes to 1e-4 of the frame's rms slope, measured slopes bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fwr_oracle as O
+from paper_1705_04298_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_04298_amd import fwr
+    fwr.load()
+    return fwr
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(F, p: O.Params, mask, B):
+    return F.Plan(p.n_sub, p.n_grid, mask, n_iter=p.n_iter, periodic=p.periodic, gamma=p.gamma,
+                  noise_var=p.noise_var, r0=p.r0, L0=p.L0, d=p.d, max_batch=B, model="sinc")
+
+
+def _rel(got, want):
+    return np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
+
+
+@pytest.mark.parametrize("n_iter,periodic", [(10, True), (0, True), (3, False), (20, True)])
+def test_sphere40_sinc_matches_oracle(F, n_iter, periodic):
+    _flush(f"[gpu] sinc 40x40 it={n_iter} periodic={periodic}")
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40_SINC, 5, dtype=np.float32)
+    p = O.Params(n_sub=40, n_grid=80, n_iter=n_iter, periodic=periodic, model="sinc")
+    plan = _plan(F, p, mask, 5)
+    got = plan.reconstruct(torch.from_numpy(slopes).cuda()).cpu().numpy().astype(np.float64)
+    for b in range(5):
+        want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
+        assert _rel(got[b], want) <= 1e-5, (b, _rel(got[b], want))
+    plan.close()
+
+
+@pytest.mark.parametrize("N,n", [(8, 4), (16, 8), (24, 12), (32, 16), (40, 20), (48, 24), (64, 32), (80, 78)])
+def test_sinc_grid_sizes_and_groups(F, N, n):
+    _flush(f"[gpu] sinc grid N={N} n={n}")
+    mask = I.random_mask(n, seed=700 + N + n)
+    slopes = I.random_slopes(3, n, seed=N + n).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=5, periodic=True, d=8.0 / n, model="sinc")
+    plan = _plan(F, p, mask, 3)
+    x = torch.from_numpy(slopes).cuda()
+    plan.set_group(1)
+    ref = plan.reconstruct(x).clone()
+    try:
+        plan.set_group(2)
+        assert torch.equal(plan.reconstruct(x), ref)
+    except F.FwrError as e:
+        assert e.status == F.FWR_E_UNSUPPORTED
+    got = ref.cpu().numpy().astype(np.float64)
+    for b in range(3):
+        want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
+        assert _rel(got[b], want) <= 1e-5, (b, _rel(got[b], want))
+    plan.close()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_sinc_extend(F, periodic):
+    _flush(f"[gpu] sinc extend periodic={periodic}")
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40_SINC, 3, start=10, dtype=np.float32)
+    p = O.Params(n_sub=40, n_grid=80, n_iter=7, periodic=periodic, model="sinc")
+    plan = _plan(F, p, mask, 3)
+    got = plan.extend(torch.from_numpy(slopes).cuda()).cpu().numpy().astype(np.float64)
+    m = mask.astype(bool)
+    for b in range(3):
+        ref = O.extend(slopes[b].astype(np.float64), mask, p)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(got[b, 0] - ref.sx).max() <= 1e-4 * scale
+        assert np.abs(got[b, 1] - ref.sy).max() <= 1e-4 * scale
+        assert np.array_equal(got[b, 0, 20:60, 20:60][m].astype(np.float32), slopes[b, 0][m])
+        assert np.array_equal(got[b, 1, 20:60, 20:60][m].astype(np.float32), slopes[b, 1][m])
+    plan.close()
+
+
+def test_sinc_unsupported_calls(F):
+    mask = I.pupil_mask(40)
+    plan = F.Plan(40, 80, mask, n_iter=2, max_batch=2, model="sinc")
+    x = torch.zeros((2, 2, 40, 40), device="cuda")
+    with pytest.raises(F.FwrError):
+        plan.reconstruct(x, start=torch.zeros((2, 2, 80, 80), device="cuda"))
+    with pytest.raises(F.FwrError):
+        plan.generate(2, 1)
+    with pytest.raises(F.FwrError):
+        F.Plan(128, 256, I.pupil_mask(128), max_batch=1, model="sinc")
+    with pytest.raises(F.FwrError):
+        F.Plan(40, 80, mask, periodic_each_iter=True, max_batch=1, model="sinc")
+    plan.close()

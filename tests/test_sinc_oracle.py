@@ -1,0 +1,103 @@
+"""The lenslet-averaging (sinc) slope model of Eq. 4 in the FP64 oracle (CPU only).
+
+Pins: the transfer function equals the continuous Shack-Hartmann measurement of single
+Fourier modes computed by Gauss-Legendre quadrature over the lenslet edges; its real-space
+kernel is real and it vanishes exactly on its singular set; under this model the loop keeps
+the measurement, its residual does not increase, a true extension is a fixed point, Eq. 5
+zeroes the line sums, and the LSQ final filter recovers a band-limited phase up to piston.
+"""
+import numpy as np
+import pytest
+
+from oracle import fwr_oracle as O
+
+
+def _quadrature_slopes(kp, lp, N, m, n):
+    """x and y edge-average differences of the mode exp(2 pi i (k' x + l' y) / N) (d = 1)
+    over cell (m, n): lenslet x in [n, n + 1], y in [m, m + 1]."""
+    t, w = np.polynomial.legendre.leggauss(40)
+    u = 0.5 * (t + 1.0)  # nodes on [0, 1]
+    w = 0.5 * w
+    mode = lambda x, y: np.exp(2j * np.pi * (kp * x + lp * y) / N)
+    sx = np.sum(w * (mode(n + 1.0, m + u) - mode(n + 0.0, m + u)))
+    sy = np.sum(w * (mode(n + u, m + 1.0) - mode(n + u, m + 0.0)))
+    return sx, sy
+
+
+@pytest.mark.parametrize("N", [16, 20])
+def test_transfer_function_matches_quadrature(N):
+    Gx, Gy = O.sinc_model(N)
+    rng = np.random.default_rng(N)
+    half = N // 2
+    for _ in range(12):
+        kp, lp = rng.integers(-half + 1, half, size=2)
+        m, n = rng.integers(0, N, size=2)
+        sx, sy = _quadrature_slopes(kp, lp, N, m, n)
+        node = np.exp(2j * np.pi * (kp * n + lp * m) / N)
+        assert abs(sx - Gx[lp % N, kp % N] * node) < 1e-12
+        assert abs(sy - Gy[lp % N, kp % N] * node) < 1e-12
+
+
+@pytest.mark.parametrize("N", [8, 10, 16])
+def test_real_kernel_and_singular_set(N):
+    Gx, Gy = O.sinc_model(N)
+    for G in (Gx, Gy):
+        assert np.abs(np.fft.ifft2(G).imag).max() < 1e-15
+    g2 = np.abs(Gx) ** 2 + np.abs(Gy) ** 2
+    S = O.sinc_singular_set(N)
+    assert np.all(g2[S] == 0.0) and np.all(g2[~S] > 1e-6)
+
+
+def _bandlimited_phase(N, seed):
+    """Real periodic phase without DC or Nyquist content."""
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    F[0, 0] = 0.0
+    if N % 2 == 0:
+        F[N // 2, :] = 0.0
+        F[:, N // 2] = 0.0
+    return np.real(np.fft.ifft2(F)) * N
+
+
+def _model_slopes(phi):
+    Gx, Gy = O.sinc_model(phi.shape[0])
+    P = np.fft.fft2(phi)
+    return np.real(np.fft.ifft2(Gx * P)), np.real(np.fft.ifft2(Gy * P))
+
+
+def test_loop_invariants_under_the_sinc_model():
+    n, N = 8, 16
+    mask = (np.random.default_rng(3).random((n, n)) < 0.8).astype(np.uint8)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=6, periodic=False, model="sinc")
+    slopes = np.random.default_rng(4).standard_normal((2, n, n))
+    r = O.extend(slopes, mask, p)
+    o = (N - n) // 2
+    m = mask.astype(bool)
+    assert np.array_equal(r.sx[o:o + n, o:o + n][m], slopes[0][m])
+    assert np.array_equal(r.sy[o:o + n, o:o + n][m], slopes[1][m])
+    assert all(b <= a + 1e-12 for a, b in zip(r.residuals, r.residuals[1:]))
+    rp = O.extend(slopes, mask, p._replace(periodic=True))
+    assert np.abs(rp.sx.sum(axis=1)).max() < 1e-12 and np.abs(rp.sy.sum(axis=0)).max() < 1e-12
+
+
+def test_true_extension_is_a_fixed_point():
+    n, N = 8, 16
+    phi = _bandlimited_phase(N, 5)
+    sx, sy = _model_slopes(phi)
+    o = (N - n) // 2
+    mask = np.ones((n, n), dtype=np.uint8)
+    mask[3:5, 3:5] = 0
+    slopes = np.stack([sx[o:o + n, o:o + n], sy[o:o + n, o:o + n]]) * mask
+    p = O.Params(n_sub=n, n_grid=N, n_iter=4, periodic=False, model="sinc")
+    r = O.extend(slopes, mask, p, start=(sx, sy))
+    assert np.abs(r.sx - sx).max() < 1e-10 and np.abs(r.sy - sy).max() < 1e-10
+
+
+def test_lsq_recovers_a_bandlimited_phase():
+    N = 16
+    phi = _bandlimited_phase(N, 6)
+    sx, sy = _model_slopes(phi)
+    Gx, Gy = O.sinc_model(N)
+    Rx, Ry = O.wiener_reconstructor(Gx, Gy, 0.0, singular=O.sinc_singular_set(N))
+    rec = O.fourier_reconstruct(sx, sy, Rx, Ry)
+    assert np.abs(rec - (phi - phi.mean())).max() < 1e-12
