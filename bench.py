@@ -126,10 +126,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = up to 16; use 1 under a profiler)")
-    ap.add_argument("--workload", choices=("sphere40", "elt128", "uneven"), default="sphere40",
+    ap.add_argument("--workload", choices=("sphere40", "elt128", "uneven", "sinc40"), default="sphere40",
                     help="sphere40: the headline 4096 x 40x40 batch; elt128: 128 x 128x128 frames on "
                          "the 256x256 multi-pass path; uneven: the mixed-size closed loop captured in a "
-                         "HIP graph (each prints its own line)")
+                         "HIP graph; sinc40: the headline batch with the lenslet-averaging slope model "
+                         "(each prints its own line)")
     ap.add_argument("--graph-steps", type=int, default=1000,
                     help="uneven workload: timed graph replays (one loop step each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -148,6 +149,8 @@ def main():
         return elt_main(args)
     if args.workload == "uneven":
         return uneven_main(args)
+    if args.workload == "sinc40":
+        return sinc_main(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (frames are independent; see the design notes "
               f"for how the batch shards): --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -266,6 +269,70 @@ def elt_main(args):
                       "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": 8000.0,
                                    "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / 8e12, "traffic": None}}),
           flush=True)
+
+
+def _gen_sinc(args):
+    start, count = args
+    return I.make_batch(I.SPHERE_40_SINC, count, start=start, dtype=np.float32)
+
+
+def _oracle_sinc(idx):
+    from oracle import fwr_oracle as O
+    p = O.Params(n_sub=N_SUB, n_grid=N_GRID, n_iter=N_ITER, periodic=True, model="sinc")
+    mask = I.pupil_mask(N_SUB)
+    return [(i, O.reconstruct(_CPU_SLOPES[i].astype(np.float64), mask, p)) for i in idx]
+
+
+def sinc_main(args):
+    """The headline batch (4096 x 40x40 -> 80x80, 10 iterations + Eq. 5 + MMSE) with the
+    lenslet-averaging slope model of Eq. 4 on the Fourier-domain kernel; parity against the FP64
+    oracle over a sample of the batch."""
+    global _CPU_SLOPES
+    import torch
+    from paper_1705_04298_amd import fwr
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(s0, min(64, args.batch - s0)) for s0 in range(0, args.batch, 64)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        slopes = np.concatenate(pool.map(_gen_sinc, jobs), axis=0)
+    sample = min(args.cpu_sample, args.batch)
+    _CPU_SLOPES = slopes
+    parts = [np.arange(sample)[w::workers] for w in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        ref = {i: ph for part in pool.map(_oracle_sinc, parts) for i, ph in part}
+    torch.cuda.set_device(0)
+    plan = fwr.Plan(N_SUB, N_GRID, I.pupil_mask(N_SUB), n_iter=N_ITER, periodic=True, max_batch=args.batch,
+                    model="sinc")
+    x = torch.from_numpy(slopes).cuda()
+    if not args.no_autotune:
+        plan.autotune(args.batch)
+    threads, fpg, lds = plan.launch_info()
+    out = torch.empty((args.batch, N_SUB + 1, N_SUB + 1), device="cuda")
+    for _ in range(args.warmup):
+        plan.reconstruct(x, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.reconstruct(x, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    got = out.cpu().numpy().astype(np.float64)
+    errs = [np.sqrt(np.mean((got[i] - w) ** 2) / np.mean(w ** 2)) for i, w in ref.items()]
+    flops = algorithmic_flops_per_frame(N_GRID, N_ITER) * args.batch
+    plan.close()
+    print(json.dumps({
+        "metric": "frames/s (40x40 SH, 10 Gerchberg iters, lenslet-averaging slope model)",
+        "value": args.batch / (ms / 1e3), "unit": "frames/s", "ms_per_step": ms, "steps": args.steps,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "4096 frames 40x40 SH, lenslet-averaging (sinc) slopes of von Karman screens, "
+                               "padded 80x80, 10 iterations + Eq.5 + MMSE", "model": "sinc",
+                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds},
+        "rms_phase_error_vs_oracle": {"frames": len(errs), "max_rel_rms": float(np.max(errs)),
+                                      "median_rel_rms": float(np.median(errs)), "tolerance": 1e-5},
+        "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / FP32_VECTOR_PEAK, "traffic": None},
+    }), flush=True)
 
 
 UNEVEN = ((24, 2048, 8.0 / 24), (40, 2048, 8.0 / 40), (64, 512, 8.0 / 64), (128, 64, 39.0 / 128))
