@@ -150,11 +150,28 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
  * always.  `d_resid` (float[B], may be NULL) receives the in-pupil misfit of
  * the last iteration, ||P (G phi - s0)|| / ||P s0|| (0 when n_iter = 0 or the
  * pupil is empty).  On-chip grids only (N <= 128); FWR_E_UNSUPPORTED otherwise.
+ * With n_iter = 0 the start is the extension: fwr_reconstruct_start then applies
+ * Eq. 2/3 to (measurement inside, start outside); it needs periodic = 0 and no
+ * residual, and fwr_extend_start needs n_iter >= 1 (FWR_E_INVAL otherwise).
  */
 fwr_status fwr_extend_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_ext,
                             float *d_resid, int32_t B);
 fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const float *d_start, float *d_phase,
                                  float *d_resid, int32_t B);
+
+/* ------------------------------------------------------------------------
+ * Comparison extension.
+ *
+ * fwr_hudgin_extend: the "Hudgin extension" the paper compares against (Sec. 3.2):
+ * x slopes repeated up and down each column and y slopes left and right along each
+ * row from the edge of the pupil, then Eq. 5.  Every cell outside the pupil takes the
+ * slope of the nearest in-pupil cell of its column (x) or row (y), the upper / left one
+ * on a tie (this also fills the central obstruction); a line without in-pupil cells is
+ * zero.  d_slopes: float[B][2][n][n]; d_ext: float[B][2][N][N].  On-chip Fried plans only
+ * (FWR_E_UNSUPPORTED otherwise).  The phase of this extension is fwr_reconstruct_start on
+ * a plan with n_iter = 0 and periodic = 0 with d_ext as the start.
+ */
+fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B);
 
 /* ------------------------------------------------------------------------
  * Mixed batches and synthetic frames.

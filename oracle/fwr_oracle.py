@@ -245,6 +245,50 @@ def enforce_periodicity(sx: np.ndarray, sy: np.ndarray):
     return sx, sy
 
 
+def hudgin_extend(s0x: np.ndarray, s0y: np.ndarray, P: np.ndarray):
+    """The comparison extension of Sec. 3.2 ("Hudgin extension"): the x slopes are extended up
+    and down each column and the y slopes left and right along each row by repeating the slope
+    at the edge of the pupil; then Eq. 5 is imposed (the paper always does with this method).
+
+    Reading where the paper is silent (central obstruction): every cell outside the pupil takes
+    the slope of the nearest in-pupil cell of its column (x) or row (y), the one above or to the
+    left on a tie; a line without in-pupil cells stays zero.  Returns (s_x, s_y) on the grid.
+    """
+    N = P.shape[0]
+    sx = np.array(s0x, dtype=np.float64)
+    sy = np.array(s0y, dtype=np.float64)
+    for c in range(N):  # columns: x slopes
+        valid = np.flatnonzero(P[:, c])
+        if valid.size == 0:
+            sx[:, c] = 0.0
+            continue
+        for m in range(N):
+            if not P[m, c]:
+                dist = np.abs(valid - m)
+                sx[m, c] = s0x[valid[np.argmin(dist)], c]  # argmin takes the first (upper) on a tie
+    for r in range(N):  # rows: y slopes
+        valid = np.flatnonzero(P[r, :])
+        if valid.size == 0:
+            sy[r, :] = 0.0
+            continue
+        for n in range(N):
+            if not P[r, n]:
+                dist = np.abs(valid - n)
+                sy[r, n] = s0y[r, valid[np.argmin(dist)]]
+    return enforce_periodicity(sx, sy)
+
+
+def reconstruct_hudgin(slopes: np.ndarray, mask: np.ndarray, p: Params) -> np.ndarray:
+    """Hudgin extension followed by the final reconstruction (Eq. 2 with the Eq. 3 filter);
+    the (n+1) x (n+1) node window, as `reconstruct`."""
+    s0x, s0y, P = padded_measurement(slopes, mask, p.n_grid)
+    sx, sy = hudgin_extend(s0x, s0y, P)
+    Rx, Ry = final_filters(p)
+    phi = fourier_reconstruct(sx, sy, Rx, Ry)
+    o = pupil_offset(p.n_sub, p.n_grid)
+    return phi[o:o + p.n_sub + 1, o:o + p.n_sub + 1]
+
+
 class GerchbergResult(NamedTuple):
     sx: np.ndarray
     sy: np.ndarray

@@ -10,12 +10,14 @@
 
 #include "../../include/fwr.h"
 #include <complex>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
 
 #include "fourier.h"
 #include "gen.h"
+#include "hudgin.h"
 #include "multipass.h"
 #include "onchip.h"
 
@@ -52,6 +54,7 @@ struct fwr_plan_s {
   bool multipass = false;
   fwr::MPArgs mp{};
   const uint8_t *dmask = nullptr;  // [n][n] valid subapertures on the device (generator)
+  const int32_t *hudgin_src = nullptr;  // [2][N][N] source cells of the Hudgin extension (on-chip plans)
   double d = 0.0;                  // lenslet pitch [m]
 };
 
@@ -231,7 +234,28 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const size_t b_tw = tw.size() * sizeof(float2);
   const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
   const size_t off_dmask = off_codes + codes.size() * sizeof(uint32_t);
-  const size_t total = off_dmask + (size_t)n * n;
+  // Hudgin extension: the nearest in-pupil cell of the column (x) / row (y), upper / left on a tie
+  std::vector<int32_t> hsrc(2 * (size_t)N * N, -1);
+  for (int m = 0; m < N; ++m)
+    for (int c = 0; c < N; ++c) {
+      int best = -1, bd = N + 1;
+      for (int r = 0; r < N; ++r)
+        if (in_pupil(r, c) && std::abs(r - m) < bd) {
+          bd = std::abs(r - m);
+          best = (r - o) * n + (c - o);
+        }
+      hsrc[(size_t)m * N + c] = best;
+      best = -1;
+      bd = N + 1;
+      for (int q = 0; q < N; ++q)
+        if (in_pupil(m, q) && std::abs(q - c) < bd) {
+          bd = std::abs(q - c);
+          best = (m - o) * n + (q - o);
+        }
+      hsrc[(size_t)N * N + (size_t)m * N + c] = best;
+    }
+  const size_t off_hudgin = (off_dmask + (size_t)n * n + 15) & ~size_t(15);
+  const size_t total = off_hudgin + hsrc.size() * sizeof(int32_t);
   std::vector<uint8_t> dmask((size_t)n * n);
   for (size_t i = 0; i < dmask.size(); ++i) dmask[i] = p.mask[i] ? 1 : 0;
   char *mem = nullptr;
@@ -245,6 +269,8 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   if (e == hipSuccess)
     e = hipMemcpy(mem + off_codes, codes.data(), codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(mem + off_dmask, dmask.data(), dmask.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_hudgin, hsrc.data(), hsrc.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = fwr::hudgin_prepare(N);
   if (e != hipSuccess) {
     (void)hipFree(mem);
     delete plan;
@@ -264,6 +290,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   plan->tw_lane = reinterpret_cast<const float2 *>(mem + off_tw);
   plan->codes = reinterpret_cast<const uint32_t *>(mem + off_codes);
   plan->dmask = reinterpret_cast<const uint8_t *>(mem + off_dmask);
+  plan->hudgin_src = reinterpret_cast<const int32_t *>(mem + off_hudgin);
   plan->d = p.d;
   *out = plan;
   return FWR_OK;
@@ -286,7 +313,10 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) | (extend ? fwr::kFourierExtend : 0);
     return fwr::fourier_launch(plan->N, a, st, plan->frames) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
-  if (start != nullptr && plan->n_iter == 0) return FWR_E_INVAL;
+  // with no iteration the start is the extension itself: Eq. 2/3 of (measurement inside, start
+  // outside); the extended-slope output, Eq. 5 and the residual need iterations
+  if (start != nullptr && plan->n_iter == 0 && (extend || resid != nullptr || (plan->flags & fwr::kFlagPeriodic)))
+    return FWR_E_INVAL;
   if (plan->multipass) {
     fwr::MPArgs a = plan->mp;
     a.slopes = in;
@@ -398,6 +428,23 @@ fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, ui
     e = fwr::gen_launch(plan->N, g, plan->stream);
   }
   return e == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+}
+
+fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (plan->hudgin_src == nullptr) return FWR_E_UNSUPPORTED;
+  if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
+  if (B == 0) return FWR_OK;
+  if (d_slopes == nullptr || d_ext == nullptr) return FWR_E_INVAL;
+  fwr::HudginArgs a{};
+  a.slopes = d_slopes;
+  a.out = d_ext;
+  a.src_x = plan->hudgin_src;
+  a.src_y = plan->hudgin_src + (size_t)plan->N * plan->N;
+  a.B = B;
+  a.n = plan->n;
+  a.N = plan->N;
+  return fwr::hudgin_launch(a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
 fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {

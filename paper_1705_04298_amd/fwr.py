@@ -34,7 +34,7 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
-            "fwr_plan_autotune")
+            "fwr_plan_autotune", "fwr_hudgin_extend")
 CNN_PARAMS = 47714
 
 
@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_set_stream.restype = ctypes.c_int
     lib.fwr_cnn_destroy.argtypes = [vp]
     lib.fwr_cnn_destroy.restype = ctypes.c_int
+    lib.fwr_hudgin_extend.argtypes = [vp, vp, vp, i32]
+    lib.fwr_hudgin_extend.restype = ctypes.c_int
     lib.fwr_plan_set_group.argtypes = [vp, i32]
     lib.fwr_plan_set_group.restype = ctypes.c_int
     lib.fwr_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
@@ -293,6 +295,19 @@ class Plan:
 
     def launch_info(self):
         return fwr_plan_launch_info(self._h)
+
+    def hudgin_extend(self, slopes, out=None):
+        """The comparison (Hudgin) extension with Eq. 5: extended slopes [B, 2, N, N]."""
+        import torch
+        B = slopes.shape[0]
+        self._check(slopes, (B, 2, self.n_sub, self.n_sub), "slopes")
+        if out is None:
+            out = torch.empty((B, 2, self.n_grid, self.n_grid), device=slopes.device, dtype=torch.float32)
+        self._check(out, (B, 2, self.n_grid, self.n_grid), "out")
+        st = load().fwr_hudgin_extend(self._h, ctypes.c_void_p(slopes.data_ptr()), ctypes.c_void_p(out.data_ptr()), B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_hudgin_extend")
+        return out
 
     def generate(self, B: int, seed: int, first_frame: int = 0, r0: float = 0.15, L0: float = 25.0,
                  sigma: float = 0.05, counter=None, slopes=None, phase=None, with_phase: bool = False):
