@@ -1,0 +1,166 @@
+"""Closed-loop AO harness around the library's reconstruction (Sec. 4.2).
+
+Many independent loops run side by side, one frame per loop and step:
+  * turbulence: a periodic von Karman screen per loop (M x M samples of the lenslet pitch,
+    host-generated, seeded) in frozen flow along x, `shift` lenslet pitches per step (Table 1:
+    10 m/s at 1 kHz over 0.2 m lenslets is 0.05); the sub-sample shift is a Fourier shift of the
+    periodic screen along x, which keeps its statistics exactly;
+  * the deformable mirror holds a phase on the (n+1) x (n+1) Fried nodes (a perfect mirror);
+  * the sensor measures the Fried slopes of (turbulence - mirror) on the valid subapertures,
+    plus white noise;
+  * the reconstruction is the library's (Gerchberg with `n_iter`, zero padding = 0 iterations,
+    or the Hudgin extension);
+  * an integrator with a one-frame delay: the command computed from the measurement of step t
+    acts from step t + 1, mirror += gain x reconstruction.
+The figure of merit is the residual phase rms on the pupil nodes (piston removed) over the last
+`steps - settle` steps (Sec. 4.2 exposes the camera for 200 closed-loop steps) and the
+corresponding Strehl ratio in K band (Marechal approximation, phase scaled by 0.5 / 2.2 um).
+
+The screen motion, the sensor, the mirror update and the statistics are tensor plumbing around the
+library calls (the simulated system, not the method).
+
+    python -m paper_1705_04298_amd.closedloop --loops 1024 --steps 400
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+
+import numpy as np
+
+from . import fwr
+from . import inputs as I
+
+N_SUB, N_GRID = 40, 80
+K_BAND_SCALE = 0.5 / 2.2  # phase at 500 nm -> phase at 2.2 um
+
+
+def _screen(args):
+    seed, M, d, r0, L0 = args
+    return I.vk_screen(np.random.default_rng([I.SEED_BASE, 7, seed]), M, d, r0, L0).astype(np.float32)
+
+
+def screens(loops: int, M: int = 256, d: float = 0.2, r0: float = 0.15, L0: float = 30.0, seed0: int = 0,
+            workers: int = 0) -> np.ndarray:
+    workers = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(workers) as pool:
+        return np.stack(pool.map(_screen, [(seed0 + i, M, d, r0, L0) for i in range(loops)]))
+
+
+class Loop:
+    """`loops` closed loops on device tensors.  `method`: "gerchberg" or "hudgin"."""
+
+    def __init__(self, scr, n_iter=1, periodic=False, gain=0.5, sigma=0.05, shift=0.05, method="gerchberg",
+                 n=N_SUB, N=N_GRID, seed=0):
+        import torch
+        self.torch = torch
+        scr = scr if isinstance(scr, torch.Tensor) else torch.from_numpy(scr).cuda()
+        self.B, self.M = scr.shape[0], scr.shape[2]
+        # rows 0..n of each screen, Fourier transformed along x once
+        self.spec = torch.fft.rfft(scr[:, : n + 1, :].double(), dim=2)
+        self.kx = torch.arange(self.spec.shape[2], device="cuda", dtype=torch.float64) * (2 * math.pi / self.M)
+        self.n, self.N, self.gain, self.sigma, self.shift = n, N, gain, sigma, shift
+        self.method = method
+        mask = I.pupil_mask(n)
+        self.mask = torch.from_numpy(mask.astype(np.float32)).cuda()
+        self.nodes = torch.from_numpy(I.pupil_nodes(mask)).cuda()
+        if method == "hudgin":
+            self.plan = fwr.Plan(n, N, mask, n_iter=0, periodic=False, max_batch=self.B)
+            self.ext = torch.empty((self.B, 2, N, N), device="cuda")
+        else:
+            self.plan = fwr.Plan(n, N, mask, n_iter=n_iter, periodic=periodic, max_batch=self.B)
+        self.dm = torch.zeros((self.B, n + 1, n + 1), device="cuda")
+        self.rec = torch.empty((self.B, n + 1, n + 1), device="cuda")
+        self.gen = torch.Generator(device="cuda").manual_seed(seed)
+        self.t = 0
+
+    def turbulence(self, t):
+        """Rows and columns 0..n of the screen moved by `shift * t` samples: s(x + shift * t)."""
+        torch = self.torch
+        x0 = math.fmod(self.shift * t, self.M)
+        ramp = torch.polar(torch.ones_like(self.kx), self.kx * x0)
+        row = torch.fft.irfft(self.spec * ramp, n=self.M, dim=2)
+        return row[:, :, : self.n + 1].float().contiguous()
+
+    def measure(self, res, noise=None):
+        torch = self.torch
+        a, b, c, e = res[:, :-1, :-1], res[:, :-1, 1:], res[:, 1:, :-1], res[:, 1:, 1:]
+        s = torch.stack([0.5 * ((b - a) + (e - c)), 0.5 * ((c - a) + (e - b))], dim=1)
+        if noise is None:
+            noise = torch.randn(s.shape, device="cuda", generator=self.gen) * self.sigma
+        return ((s + noise) * self.mask).contiguous()
+
+    def reconstruct(self, slopes):
+        if self.method == "hudgin":
+            self.plan.hudgin_extend(slopes, self.ext)
+            return self.plan.reconstruct(slopes, self.rec, start=self.ext)
+        return self.plan.reconstruct(slopes, self.rec)
+
+    def step(self, noise=None):
+        """One loop step; returns the residual phase (turbulence - mirror) it measured."""
+        res = self.turbulence(self.t) - self.dm
+        rec = self.reconstruct(self.measure(res, noise))
+        self.dm += self.gain * rec  # acts from the next step: one frame of delay
+        self.t += 1
+        return res
+
+    def residual_rms(self, res):
+        v = res[:, self.nodes]
+        v = v - v.mean(dim=1, keepdim=True)
+        return (v * v).mean(dim=1).sqrt()
+
+    def close(self):
+        self.plan.close()
+
+
+def run(scr, steps=400, settle=200, **kw):
+    """Mean residual rms [rad at 500 nm] over steps >= settle, the K-band Strehl, and the
+    short-exposure residual rms of every step (mean over the loops)."""
+    loop = Loop(scr, **kw)
+    acc, count, series = 0.0, 0, []
+    for t in range(steps):
+        res = loop.step()
+        var = float((loop.residual_rms(res) ** 2).mean())
+        series.append(math.sqrt(var))
+        if t >= settle:
+            acc += var
+            count += 1
+    loop.close()
+    var = acc / max(count, 1)
+    return {"residual_rms_rad": math.sqrt(var), "strehl_k": math.exp(-var * K_BAND_SCALE ** 2), "series": series}
+
+
+def table(loops=1024, steps=400, shift=0.05, log=print):
+    import torch
+    scr = torch.from_numpy(screens(loops)).cuda()
+    rows = []
+    configs = [("gerchberg", 0, False), ("hudgin", 0, True)] + [("gerchberg", k, p) for p in (False, True)
+                                                               for k in (1, 2, 3, 5, 10)]
+    for method, k, periodic in configs:
+        r = run(scr, steps=steps, n_iter=k, periodic=periodic, method=method, shift=shift)
+        r.update({"method": method, "n_iter": k, "periodic": periodic})
+        rows.append(r)
+        early = " ".join(f"{r['series'][t]:.3f}" for t in (0, 1, 2, 4, 8, 16, 32, 64) if t < steps)
+        log(f"[closedloop] {method:9s} it={k:2d} periodic={periodic}: residual {r['residual_rms_rad']:.4f} rad, "
+            f"K Strehl {100 * r['strehl_k']:.2f} %; steps 0,1,2,4,8,16,32,64: {early}")
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--loops", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--shift", type=float, default=0.05, help="frozen-flow shift per step [lenslet pitches]")
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    rows = table(args.loops, args.steps, args.shift, log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps({"loops": args.loops, "steps": args.steps, "shift": args.shift, "rows": rows}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
