@@ -108,8 +108,11 @@ __device__ __forceinline__ float select_bits(bool c, float a, float b) {
   return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
 }
 
-// EACH: Eq. 5 after every iteration (flag kFlagPeriodicEach)
-template <int N, bool EACH, int PAIRS>
+// EACH: Eq. 5 after every iteration (flag kFlagPeriodicEach).
+// WIN: the pruned loop of the 2x-padded window (n = N/2, o = N/4) with the window fixed at
+// compile time, so that the zero lines and columns outside it fold away (launched only
+// for such plans without start values or the extended-slope output).
+template <int N, bool EACH, int PAIRS, bool WIN = false>
 __global__ __launch_bounds__((Group<N, PAIRS>::THREADS))
 __attribute__((amdgpu_waves_per_eu(Group<N, PAIRS>::WAVES_PER_SIMD)))
 void gerchberg_onchip_kernel(OnchipArgs a) {
@@ -137,7 +140,21 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const bool active = 2 * (PAIRS * int(blockIdx.x) + half) < a.B;
   const int fa = active ? 2 * (PAIRS * int(blockIdx.x) + half) : 0;
   const bool hasB = active && fa + 1 < a.B;
-  const int n = a.n, o = a.o;
+  const int n = WIN ? N / 2 : a.n, o = WIN ? N / 4 : a.o;
+  // with WIN: in-lane slots k whose node columns 4k + j (some lane j) meet the window
+  // [o, o+n] (the support of q2), and the window plus one column either side (the
+  // stencil's reach)
+  constexpr auto kin_w = [](int k) { return !WIN || (4 * k + 3 >= N / 4 && 4 * k <= 3 * N / 4); };
+  constexpr auto kin_r = [](int k) { return !WIN || (4 * k + 3 >= N / 4 - 1 && 4 * k <= 3 * N / 4 + 1); };
+  // q2 is zero at the nodes of a window slot that lie outside the window (the lanes of the
+  // two edge slots); their neighbour slots beyond the reach are not kept up to date
+  auto clip_w = [&](float2 &v, int k) {
+    if (WIN && (4 * k < N / 4 || 4 * k + 3 > 3 * N / 4)) {
+      const int nn = 4 * k + j;
+      const bool in = nn >= N / 4 && nn <= 3 * N / 4;
+      v = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+    }
+  };
   const int up = line == 0 ? N - 1 : line - 1;    // row m - 1
   const int dn = line == N - 1 ? 0 : line + 1;    // row m + 1
 
@@ -171,6 +188,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     const float sgn3 = pass == 0 ? 1.f : -1.f;  // r = s_x - s_y
 #pragma unroll
     for (int k = 0; k < T; ++k) {
+      if (!kin_w(k)) continue;  // no pupil cell touches these nodes
       const uint32_t c = code_of(k);
       const int nn = 4 * k + j;
       const int nl = nn == 0 ? N - 1 : nn - 1;
@@ -193,6 +211,18 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const int f0row = (in_rows ? line - o : 0) * P + T * j;
   const float rowf = in_rows ? 1.f : 0.f;
 
+  // Without start values, per-iteration Eq. 5 or the extended-slope output, the row
+  // passes are pruned to the window.  q2 = G^T s where s differs from the model slopes
+  // G phi only inside the pupil, and phi itself came from q2_prev through 1 / |G|^2, so
+  // q2 = q2_prev (zero outside the window rows, by induction from F0) plus G^T of
+  // in-pupil differences (window rows again); G^T vanishes on the singular set, so
+  // nothing is lost there.  The forward row transforms run on the window rows o..o+n,
+  // the inverse ones on those rows and one more on either side (the stencil's
+  // neighbours); the other lines carry zeros.
+  const bool prune = WIN || (!EACH && !(a.flags & kFlagExtend) && a.start == nullptr);
+  const bool row_w = !prune || in_rows;
+  const bool row_r1 = !prune || unsigned((line - (o - 1) + N) % N) < unsigned(n + 3);
+
   const bool want_resid = a.resid != nullptr && a.n_iter > 0;
   if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) {
     a.resid[fa] = 0.f;
@@ -203,15 +233,19 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const int jp = (j + 1) & 3, jm = (j + 3) & 3;
   const int carry = j == 3 ? 1 : 0, borrow = j == 0 ? 1 : 0;
 
-  // ---- Fourier step: x holds q2 (row layout) on entry, phi on exit
-  auto solve = [&](float2 *x, const float *h) {
-    line_fft_fwd<T>(x, tw, j, q);
+  // ---- Fourier step: x holds q2 (row layout) on entry, phi on exit.  Row lines with
+  // `fwd` false must hold zeros (they are written as such); with `inv` false the line's
+  // phi is not computed.
+  // `loop` (a compile-time literal at each call): the transform of a window-supported q2
+  // whose result is needed on the window rows and one row either side.
+  auto solve = [&](float2 *x, const float *h, bool fwd, bool inv, bool loop) {
+    if (fwd) line_fft_fwd<T>(x, tw, j, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
     __syncthreads();
     float2 y[T];
 #pragma unroll
-    for (int k = 0; k < T; ++k) y[k] = buf[(4 * k + j) * P + line];
+    for (int k = 0; k < T; ++k) y[k] = loop && !kin_w(k) ? make_float2(0.f, 0.f) : buf[(4 * k + j) * P + line];
     line_fft_fwd<T>(y, tw, j, q);
     const float *ht = h + t * T;  // thread-contiguous: one address, immediate offsets
 #pragma unroll
@@ -222,11 +256,15 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     }
     line_fft_inv<T>(y, tw, j, q);
 #pragma unroll
-    for (int k = 0; k < T; ++k) buf[(4 * k + j) * P + line] = y[k];
+    for (int k = 0; k < T; ++k) {
+      if (loop ? kin_r(k) : kin_w(k)) buf[(4 * k + j) * P + line] = y[k];
+    }
     __syncthreads();
+    if (inv) {
 #pragma unroll
-    for (int k = 0; k < T; ++k) x[k] = buf[line * P + T * j + k];
-    line_fft_inv<T>(x, tw, j, q);
+      for (int k = 0; k < T; ++k) x[k] = buf[line * P + T * j + k];
+      line_fft_inv<T>(x, tw, j, q);
+    }
   };
 
   // Only k = T-1 (for n + 1) and k = 0 (for n - 1) can wrap; keeping the wrap
@@ -241,30 +279,42 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   // ---- fast stencil: phi (x) -> q2 (x), measured slopes inside the pupil via F0
   auto stencil = [&](float2 *x) {
 #pragma unroll
-    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
+    for (int k = 0; k < T; ++k) {
+      if (kin_r(k)) buf[line * P + T * j + k] = x[k];
+    }
     // keep the per-node weights from being hoisted out of the iteration loop
     // as 4T live float registers: they are re-derived from 3 code words here
 #pragma unroll
     for (int w = 0; w < (T + 7) / 8; ++w) asm volatile("" : "+v"(codes[w]));
     __syncthreads();
+    if (row_w) {
 #pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const int sp = slot_p(k), sm = slot_m(k);
-      const float2 d1 = buf[dn * P + sp];  // (m+1, n+1)
-      const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
-      const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
-      const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
-      const uint32_t c = code_of(k);
-      float2 r;
-      if constexpr (C::F0_IN_LDS) {
-        const float2 fv = f0rows[f0row + k];  // clamped address: always a valid read
-        r = make_float2(fv.x * rowf, fv.y * rowf);
-      } else {
-        r = f0[k];
+      for (int k = 0; k < T; ++k) {
+        if (!kin_w(k)) {
+          x[k] = make_float2(0.f, 0.f);
+          continue;
+        }
+        const int sp = slot_p(k), sm = slot_m(k);
+        const float2 d1 = buf[dn * P + sp];  // (m+1, n+1)
+        const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
+        const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
+        const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
+        const uint32_t c = code_of(k);
+        float2 r;
+        if constexpr (C::F0_IN_LDS) {
+          const float2 fv = f0rows[f0row + k];  // clamped address: always a valid read
+          r = make_float2(fv.x * rowf, fv.y * rowf);
+        } else {
+          r = f0[k];
+        }
+        x[k] = outside_sum(r, x[k], d1, d2, d3, d4, c);
+        clip_w(x[k], k);
+        // bound the neighbour reads in flight (4 per node)
+        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
-      x[k] = outside_sum(r, x[k], d1, d2, d3, d4, c);
-      // bound the neighbour reads in flight (4 per node)
-      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < T; ++k) x[k] = make_float2(0.f, 0.f);
     }
     __syncthreads();
   };
@@ -287,7 +337,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   constexpr bool EY_IN_F0 = !EACH;
   auto final_step = [&](float2 *x, bool fix, bool write) -> bool {
 #pragma unroll
-    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
+    for (int k = 0; k < T; ++k) {
+      if (kin_r(k)) buf[line * P + T * j + k] = x[k];
+    }
     __syncthreads();
     const unsigned wrow = unsigned(line >= o && line < o + n ? line - o : 0) * unsigned(n);
     const size_t gplane = (size_t)N * N;
@@ -295,62 +347,72 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     float2 rowacc = make_float2(0.f, 0.f);
     float ra = 0.f, rb = 0.f, na = 0.f, nb = 0.f;  // in-pupil misfit and measurement energy
     float2 DY[EY_IN_F0 ? 1 : T];
+    if (row_w) {  // (pruned: the other lines have no pupil cell and q2 = 0 there)
 #pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const int nn = 4 * k + j;
-      const uint32_t c4 = code_of(k);
-      const bool meas = !(c4 & 1u);
-      const unsigned widx = wrow + unsigned(nn >= o && nn < o + n ? nn - o : 0);
-      // measured slopes, exactly zero outside the pupil (whatever the input holds there)
-      const float mxa = select_bits(meas, sa[widx], 0.f), mya = select_bits(meas, sa[uplane + widx], 0.f);
-      const float mxb = select_bits(meas, sbb[widx] * bflag, 0.f);
-      const float myb = select_bits(meas, sbb[uplane + widx] * bflag, 0.f);
-      const int sp = slot_p(k), sm = slot_m(k);
-      const float2 ph = x[k];
-      const float2 b = buf[line * P + sp];       // (m, n+1)
-      const float2 c = buf[dn * P + T * j + k];  // (m+1, n)
-      const float2 d1 = buf[dn * P + sp];        // (m+1, n+1)
-      // cell (m, n): s_x = (b - a + d - c) / 2, s_y = (c - a + d - b) / 2
-      const float2 gx = make_float2(0.5f * ((b.x - ph.x) + (d1.x - c.x)), 0.5f * ((b.y - ph.y) + (d1.y - c.y)));
-      const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
-      const float2 ex = make_float2(select_bits(meas, mxa - gx.x, 0.f), select_bits(meas, mxb - gx.y, 0.f));
-      const float2 ey = make_float2(select_bits(meas, mya - gy.x, 0.f), select_bits(meas, myb - gy.y, 0.f));
-      if (want_resid) {
-        ra = fmaf(ex.x, ex.x, fmaf(ey.x, ey.x, ra));
-        rb = fmaf(ex.y, ex.y, fmaf(ey.y, ey.y, rb));
-        na = fmaf(mxa, mxa, fmaf(mya, mya, na));
-        nb = fmaf(mxb, mxb, fmaf(myb, myb, nb));
-      }
-      rowacc = cadd(rowacc, ex);
-      if (write && active) {
-        const size_t idx = (size_t)line * N + nn;
-        ea[idx] = select_bits(meas, mxa, gx.x);
-        ea[gplane + idx] = select_bits(meas, mya, gy.x);
-        if (hasB) {
-          ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
-          ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
+      for (int k = 0; k < T; ++k) {
+        if (!kin_w(k)) {
+          x[k] = make_float2(0.f, 0.f);
+          continue;
         }
-      } else {
-        const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
-        const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
-        const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
-        float2 r;
-        if constexpr (C::F0_IN_LDS) {
-          const float2 fv = f0rows[f0row + k];
-          r = make_float2(fv.x * rowf, fv.y * rowf);
+        const int nn = 4 * k + j;
+        const uint32_t c4 = code_of(k);
+        const bool meas = !(c4 & 1u);
+        const unsigned widx = wrow + unsigned(nn >= o && nn < o + n ? nn - o : 0);
+        // measured slopes, exactly zero outside the pupil (whatever the input holds there)
+        const float mxa = select_bits(meas, sa[widx], 0.f), mya = select_bits(meas, sa[uplane + widx], 0.f);
+        const float mxb = select_bits(meas, sbb[widx] * bflag, 0.f);
+        const float myb = select_bits(meas, sbb[uplane + widx] * bflag, 0.f);
+        const int sp = slot_p(k), sm = slot_m(k);
+        const float2 ph = x[k];
+        const float2 b = buf[line * P + sp];       // (m, n+1)
+        const float2 c = buf[dn * P + T * j + k];  // (m+1, n)
+        const float2 d1 = buf[dn * P + sp];        // (m+1, n+1)
+        // cell (m, n): s_x = (b - a + d - c) / 2, s_y = (c - a + d - b) / 2
+        const float2 gx = make_float2(0.5f * ((b.x - ph.x) + (d1.x - c.x)), 0.5f * ((b.y - ph.y) + (d1.y - c.y)));
+        const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
+        const float2 ex = make_float2(select_bits(meas, mxa - gx.x, 0.f), select_bits(meas, mxb - gx.y, 0.f));
+        const float2 ey = make_float2(select_bits(meas, mya - gy.x, 0.f), select_bits(meas, myb - gy.y, 0.f));
+        if (want_resid) {
+          ra = fmaf(ex.x, ex.x, fmaf(ey.x, ey.x, ra));
+          rb = fmaf(ex.y, ex.y, fmaf(ey.y, ey.y, rb));
+          na = fmaf(mxa, mxa, fmaf(mya, mya, na));
+          nb = fmaf(mxb, mxb, fmaf(myb, myb, nb));
+        }
+        rowacc = cadd(rowacc, ex);
+        if (write && active) {
+          const size_t idx = (size_t)line * N + nn;
+          ea[idx] = select_bits(meas, mxa, gx.x);
+          ea[gplane + idx] = select_bits(meas, mya, gy.x);
+          if (hasB) {
+            ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
+            ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
+          }
         } else {
-          r = f0[k];
+          const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
+          const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
+          const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
+          float2 r;
+          if constexpr (C::F0_IN_LDS) {
+            const float2 fv = f0rows[f0row + k];
+            r = make_float2(fv.x * rowf, fv.y * rowf);
+          } else {
+            r = f0[k];
+          }
+          x[k] = outside_sum(r, ph, d1, d2, d3, d4, c4);
+        clip_w(x[k], k);
         }
-        x[k] = outside_sum(r, ph, d1, d2, d3, d4, c4);
+        if constexpr (EY_IN_F0 && C::F0_IN_LDS) {
+          if (in_rows) f0rows[f0row + k] = ey;  // after this thread's last read of the slot
+        } else if constexpr (EY_IN_F0) {
+          f0[k] = ey;
+        } else {
+          DY[k] = ey;
+        }
+        if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (EY_IN_F0 && C::F0_IN_LDS) {
-        if (in_rows) f0rows[f0row + k] = ey;  // after this thread's last read of the slot
-      } else if constexpr (EY_IN_F0) {
-        f0[k] = ey;
-      } else {
-        DY[k] = ey;
-      }
-      if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < T; ++k) x[k] = make_float2(0.f, 0.f);
     }
     if (want_resid) {  // block reduction of the four sums (fixed order), then one write per frame
       constexpr int PARTS = FULL_WAVES ? C::THREADS / 64 : C::THREADS;
@@ -486,7 +548,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   }
 
   for (int it = 0; it < a.n_iter; ++it) {
-    solve(x, a.h_loop);
+    solve(x, a.h_loop, row_w, row_r1, WIN);
     if (it == a.n_iter - 1) break;
     if constexpr (EACH) final_step(x, true, false);
     else stencil(x);
@@ -500,7 +562,8 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   } else if (a.n_iter > 0) {
     stencil(x);
   }
-  solve(x, a.h_final);
+  // the output is the window rows; with Eq. 5 the border rows 0 and N-1 carry forcing
+  solve(x, a.h_final, row_w || (fix_final && (line == 0 || line == N - 1)), row_w, false);
 
   // (n+1) x (n+1) node window
   if (active && line >= o && line <= o + n) {
@@ -525,6 +588,13 @@ constexpr bool pairs_instantiated() {
   return PAIRS == 1 || (Group<N, PAIRS>::THREADS <= 1024 && N <= 80);
 }
 
+// the compile-time window variant exists for every launch shape, so that the arithmetic
+// of a frame pair does not depend on the number of pairs per workgroup
+template <int PAIRS>
+constexpr bool win_instantiated() {
+  return true;
+}
+
 template <int N, int PAIRS>
 hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
   if constexpr (!pairs_instantiated<N, PAIRS>()) {
@@ -539,6 +609,13 @@ hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
       else
         return hipErrorInvalidValue;
     } else {
+      const bool win = a.n == N / 2 && a.o == N / 4 && a.start == nullptr && (a.flags & kFlagExtend) == 0;
+      if constexpr (win_instantiated<PAIRS>()) {
+        if (win) {
+          hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false, PAIRS, true>), grid, block, dyn, s, a);
+          return hipGetLastError();
+        }
+      }
       hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false, PAIRS>), grid, block, dyn, s, a);
     }
     return hipGetLastError();
@@ -563,11 +640,14 @@ hipError_t prepare_pairs(int n) {
   } else {
     // dynamic LDS above the default 64 KiB window must be requested explicitly
     const int dyn = Onchip<N>::F0_IN_LDS ? PAIRS * (n + 1) * Onchip<N>::PITCH * 8 : 0;
-    const void *fns[2] = {reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS>),
+    const void *fns[3] = {reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS>),
                           PAIRS == 1 ? reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true, 1>)
-                                     : nullptr};
+                                     : nullptr,
+                          nullptr};
+    if constexpr (win_instantiated<PAIRS>())
+      fns[2] = reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS, true>);
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
       if (fns[i]) e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
   }
