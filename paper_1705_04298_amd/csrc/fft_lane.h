@@ -264,6 +264,44 @@ __device__ __forceinline__ float2 quad_dft_inv(float2 v, const QuadLane &q) {
   return make_float2(fmaf(q.sg1, v.x, p.x), fmaf(q.sg1, v.y, p.y));
 }
 
+// Signed quad DFTs: each radix-2 stage is one v_fmac_f32 per component with the partner
+// lane's value as its DPP source, v += c * v(partner), c = the lane's stage sign (+-1).
+// Since c^2 = 1 this is c times the standard stage output, so lane j ends with its
+// standard result times S_j = (+1, -1, -1, +1)[j] (the product of its two stage signs;
+// the lane-3 rotation between the stages is linear and carries the sign through).  The
+// caller folds S_j into its next per-element operation.  The DPP source register must
+// not have been written by a VALU instruction in the two preceding slots: the s_nop
+// gives that distance, and the second instruction reads a register the first does not
+// write.  A quad's four lanes are always active together.
+__device__ __forceinline__ void stage_xor1(float2 &v, float c) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %0, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(v.x), "+v"(v.y)
+      : "v"(c));
+}
+__device__ __forceinline__ void stage_xor2(float2 &v, float c) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %0, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(v.x), "+v"(v.y)
+      : "v"(c));
+}
+__device__ __forceinline__ float lane_sign(int j) { return (j == 1 || j == 2) ? -1.f : 1.f; }
+
+__device__ __forceinline__ float2 quad_dft_fwd_s(float2 v, const QuadLane &q) {
+  stage_xor2(v, q.sg1);
+  if (q.is3) v = make_float2(v.y, -v.x);  // * (-i)
+  stage_xor1(v, q.sg0);
+  return v;
+}
+__device__ __forceinline__ float2 quad_dft_inv_s(float2 v, const QuadLane &q) {
+  stage_xor1(v, q.sg0);
+  if (q.is3) v = make_float2(-v.y, v.x);  // * (+i)
+  stage_xor2(v, q.sg1);
+  return v;
+}
+
 // Full line transforms.  tw[4 k + j] = W_N^(j k) = exp(-2 pi i j k / N), in LDS
 // (the 16 quads of a wave read the same four entries: broadcast, no conflicts).
 template <int T>
@@ -280,6 +318,27 @@ __device__ __forceinline__ void line_fft_inv(float2 *x, const float2 *tw, int j,
   for (int k = 0; k < T; ++k) x[k] = quad_dft_inv(x[k], q);
 #pragma unroll
   for (int k = 1; k < T; ++k) x[k] = cmul_conj(x[k], tw[4 * k + j]);
+  dft<T, +1>(x);
+}
+
+// Signed line transforms (see quad_dft_fwd_s): the forward one returns lane j's values
+// times S_j; the inverse one takes unsigned input and `twi[4 k + j]` = S_j conj(tw[4 k + j])
+// (with `sj` = S_j for k = 0), so that its output is unsigned.
+template <int T>
+__device__ __forceinline__ void line_fft_fwd_s(float2 *x, const float2 *tw, int j, const QuadLane &q) {
+  dft<T, -1>(x);
+#pragma unroll
+  for (int k = 1; k < T; ++k) x[k] = cmul(x[k], tw[4 * k + j]);
+#pragma unroll
+  for (int k = 0; k < T; ++k) x[k] = quad_dft_fwd_s(x[k], q);
+}
+template <int T>
+__device__ __forceinline__ void line_fft_inv_s(float2 *x, const float2 *twi, int j, float sj, const QuadLane &q) {
+#pragma unroll
+  for (int k = 0; k < T; ++k) x[k] = quad_dft_inv_s(x[k], q);
+  x[0] = make_float2(sj * x[0].x, sj * x[0].y);
+#pragma unroll
+  for (int k = 1; k < T; ++k) x[k] = cmul(x[k], twi[4 * k + j]);
   dft<T, +1>(x);
 }
 

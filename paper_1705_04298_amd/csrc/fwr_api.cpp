@@ -176,18 +176,22 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const int T = N / 4, threads = fwr::onchip_threads(N, 1);
   static const int beta[4] = {0, 2, 1, 3};
 
-  // host tables
+  // host tables; the filters carry the lane signs the kernel's signed quad transforms
+  // leave on the spectrum: S_(c / T) of the row pass that wrote LDS column c and S_jj of
+  // the column pass, S = (+1, -1, -1, +1)
+  static const double lane_s[4] = {1.0, -1.0, -1.0, 1.0};
   std::vector<float> h_loop((size_t)T * threads), h_final((size_t)T * threads);
   for (int c = 0; c < N; ++c) {
     const int kf = (c % T) + T * beta[c / T];  // row frequency held in LDS column c
     for (int jj = 0; jj < 4; ++jj) {
       const int tt = 4 * c + jj;
+      const double sg = lane_s[c / T] * lane_s[jj];
       for (int k2 = 0; k2 < T; ++k2) {
         const int lf = k2 + T * beta[jj];      // column frequency of this output
         double hl, hf;
         filter_values(p, lf, kf, hl, hf);
-        h_loop[(size_t)tt * T + k2] = float(hl);
-        h_final[(size_t)tt * T + k2] = float(hf);
+        h_loop[(size_t)tt * T + k2] = float(sg * hl);
+        h_final[(size_t)tt * T + k2] = float(sg * hf);
       }
     }
   }

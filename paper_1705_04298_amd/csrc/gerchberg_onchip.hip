@@ -73,7 +73,7 @@ struct Group {
   static constexpr int WAVES = (THREADS + 63) / 64;
   static constexpr int WAVES_PER_SIMD =
       (WAVES + 3) / 4 > Onchip<N>::WAVES_PER_SIMD ? (WAVES + 3) / 4 : Onchip<N>::WAVES_PER_SIMD;
-  static constexpr int STATIC_LDS_BYTES = PAIRS * (Onchip<N>::TILE + 2 * N) * 8 + Onchip<N>::T * 4 * 8 +
+  static constexpr int STATIC_LDS_BYTES = PAIRS * (Onchip<N>::TILE + 2 * N) * 8 + 2 * Onchip<N>::T * 4 * 8 +
                                           PAIRS * Onchip<N>::RED * 4;
   static int lds_bytes(int n) {
     return STATIC_LDS_BYTES + (Onchip<N>::F0_IN_LDS ? PAIRS * (n + 1) * Onchip<N>::PITCH * 8 : 0);
@@ -124,6 +124,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   constexpr bool FULL_WAVES = C::THREADS % 64 == 0;
   __shared__ float red_all[PAIRS * C::RED];
   __shared__ float2 tw[T * 4];
+  __shared__ float2 twi[T * 4];  // inverse twiddles with the lane signs of the signed quad DFT
   extern __shared__ float2 f0rows_all[];  // PAIRS x [(n+1)][PITCH], lane-blocked like the tile rows
 
   // this thread's frame pair within the workgroup and its LDS
@@ -158,7 +159,13 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const int up = line == 0 ? N - 1 : line - 1;    // row m - 1
   const int dn = line == N - 1 ? 0 : line + 1;    // row m + 1
 
-  for (int i = threadIdx.x; i < T * 4; i += Group<N, PAIRS>::THREADS) tw[i] = a.tw_lane[i];
+  for (int i = threadIdx.x; i < T * 4; i += Group<N, PAIRS>::THREADS) {
+    const float2 w = a.tw_lane[i];
+    const float sg = lane_sign(i & 3);
+    tw[i] = w;
+    twi[i] = make_float2(sg * w.x, -sg * w.y);
+  }
+  const float sj = lane_sign(j);
 
   // ---- per-node constants: out-of-pupil cell bits and the in-pupil forcing F0
   const int plane = n * n;
@@ -238,15 +245,17 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   // phi is not computed.
   // `loop` (a compile-time literal at each call): the transform of a window-supported q2
   // whose result is needed on the window rows and one row either side.
+  // The signed transforms leave lane signs on the spectra: the row pass's on the LDS
+  // columns it writes, the column pass's on its own values; the filter tables carry both.
   auto solve = [&](float2 *x, const float *h, bool fwd, bool inv, bool loop) {
-    if (fwd) line_fft_fwd<T>(x, tw, j, q);
+    if (fwd) line_fft_fwd_s<T>(x, tw, j, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
     __syncthreads();
     float2 y[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) y[k] = loop && !kin_w(k) ? make_float2(0.f, 0.f) : buf[(4 * k + j) * P + line];
-    line_fft_fwd<T>(y, tw, j, q);
+    line_fft_fwd_s<T>(y, tw, j, q);
     const float *ht = h + t * T;  // thread-contiguous: one address, immediate offsets
 #pragma unroll
     for (int k = 0; k < T; ++k) {
@@ -254,7 +263,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       y[k].x *= hv;
       y[k].y *= hv;
     }
-    line_fft_inv<T>(y, tw, j, q);
+    line_fft_inv_s<T>(y, twi, j, sj, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       if (loop ? kin_r(k) : kin_w(k)) buf[(4 * k + j) * P + line] = y[k];
@@ -263,7 +272,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     if (inv) {
 #pragma unroll
       for (int k = 0; k < T; ++k) x[k] = buf[line * P + T * j + k];
-      line_fft_inv<T>(x, tw, j, q);
+      line_fft_inv_s<T>(x, twi, j, sj, q);
     }
   };
 
