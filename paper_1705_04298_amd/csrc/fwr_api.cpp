@@ -335,6 +335,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.h_final = plan->h_final;
   a.tw_lane = plan->tw_lane;
   a.codes = plan->codes;
+  a.mask = plan->dmask;
   a.B = B;
   a.n = plan->n;
   a.o = plan->o;

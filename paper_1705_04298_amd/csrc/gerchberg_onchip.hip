@@ -134,7 +134,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   float2 *const sums = sums_all + half * 2 * N;
   float *const red = red_all + half * C::RED;
   float2 *const f0rows = f0rows_all + (C::F0_IN_LDS ? half * (a.n + 1) * P : 0);
-  const int line = t >> 2;
+  // row phase: the quad's grid row; column phase: LDS column t / 4 (the same number)
+  const int col = t >> 2;
+  const int line = col;
   const int j = t & 3;
   const QuadLane q(j);
   // a pair past the batch (last workgroup) computes on pair 0's input and writes nothing
@@ -176,38 +178,114 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const unsigned uplane = unsigned(plane);
   uint32_t codes[(T + 7) / 8];
 #pragma unroll
-  for (int w = 0; w < (T + 7) / 8; ++w) codes[w] = a.codes[w * C::THREADS + t];
+  for (int w = 0; w < (T + 7) / 8; ++w) codes[w] = a.codes[w * C::THREADS + 4 * line + j];
   auto code_of = [&](int k) -> uint32_t { return (codes[k >> 3] >> (4 * (k & 7))) & 15u; };
 
   // F0 = -p(c1) + p(c2) + r(c3) - r(c4) over the in-pupil cells c1 = (m, n), c2 = (m-1, n-1),
-  // c3 = (m, n-1), c4 = (m-1, n), with p = s_x + s_y, r = s_x - s_y.  The window's x slopes,
-  // then its y slopes, are staged in the LDS tile (invalid cells read as zero).
+  // c3 = (m, n-1), c4 = (m-1, n), with p = s_x + s_y, r = s_x - s_y.  The window's x and y
+  // slopes are staged in the LDS tile with cells outside the pupil as zeros (whatever the
+  // input holds there).  The staged planes also give the measured in-pupil row sums of s_x
+  // and column sums of s_y: Eq. 5's R_m and C_n are these minus the same sums of the model
+  // slopes.
   float2 f0[T];
 #pragma unroll
   for (int k = 0; k < T; ++k) f0[k] = make_float2(0.f, 0.f);
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int i = t; i < plane; i += C::THREADS) {
-      const float va = sa[pass * plane + i];
-      const float vb = sb ? sb[pass * plane + i] : 0.f;
-      buf[i] = make_float2(va, vb);
+  for (int i = t; i < 2 * N; i += C::THREADS) sums[i] = make_float2(0.f, 0.f);
+  // four lanes per row (x plane) or column (y plane), then a quad reduction; cell (r, c) of
+  // a plane at pv[r * pw + c]
+  auto meas_sums = [&](const float2 *pv, int pw, bool rows) {
+    for (int task = t; task < 4 * n; task += C::THREADS) {
+      const int jj = task & 3, which = task >> 2;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int i = jj; i < n; i += 4) acc = cadd(acc, rows ? pv[which * pw + i] : pv[i * pw + which]);
+      acc.x += dpp_xor1(acc.x);
+      acc.y += dpp_xor1(acc.y);
+      acc.x += dpp_xor2(acc.x);
+      acc.y += dpp_xor2(acc.y);
+      if (jj == 0) sums[(rows ? N : 0) + o + which] = acc;
     }
-    __syncthreads();
-    const float sgn3 = pass == 0 ? 1.f : -1.f;  // r = s_x - s_y
+  };
+  // With the window fixed at compile time both planes are staged with a zero border (one row
+  // above and below, 4 columns left and 5 right: every cell a window slot's node touches), so
+  // that F0 is plain arithmetic on eight unconditional reads per node.
+  constexpr bool PADF0 = WIN && (N + 4) * (N + 18) / 2 <= C::TILE;
+  if constexpr (PADF0) {
+    constexpr int NW = N / 2, PL = 4, PW = NW + 9, PH = NW + 2, PP = PH * PW;
+    constexpr int CHP = (PP + C::THREADS - 1) / C::THREADS;
+    {  // all loads first, then the LDS stores
+      float va[2][CHP], vb[2][CHP];
 #pragma unroll
-    for (int k = 0; k < T; ++k) {
-      if (!kin_w(k)) continue;  // no pupil cell touches these nodes
-      const uint32_t c = code_of(k);
-      const int nn = 4 * k + j;
-      const int nl = nn == 0 ? N - 1 : nn - 1;
-      float2 f = f0[k];
-      if (!(c & 1u)) { const float2 v = buf[(line - o) * n + (nn - o)]; f = csub(f, v); }
-      if (!(c & 2u)) { const float2 v = buf[(up - o) * n + (nl - o)]; f = cadd(f, v); }
-      if (!(c & 4u)) { const float2 v = buf[(line - o) * n + (nl - o)]; f.x = fmaf(sgn3, v.x, f.x); f.y = fmaf(sgn3, v.y, f.y); }
-      if (!(c & 8u)) { const float2 v = buf[(up - o) * n + (nn - o)]; f.x = fmaf(-sgn3, v.x, f.x); f.y = fmaf(-sgn3, v.y, f.y); }
-      f0[k] = f;
+      for (int c = 0; c < CHP; ++c) {
+        const int i = t + c * C::THREADS;
+        const int r = i / PW - 1, cc = i % PW - PL;
+        const bool inside = i < PP && r >= 0 && r < NW && cc >= 0 && cc < NW;
+        const int gi = inside ? r * NW + cc : 0;
+        const bool v = inside && a.mask[gi] != 0;
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl) {
+          const float xa = sa[pl * plane + gi], xb = sbb[pl * plane + gi];
+          va[pl][c] = v ? xa : 0.f;
+          vb[pl][c] = v && hasB ? xb : 0.f;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CHP; ++c) {
+        const int i = t + c * C::THREADS;
+        if (i < PP) {
+          buf[i] = make_float2(va[0][c], vb[0][c]);
+          buf[PP + i] = make_float2(va[1][c], vb[1][c]);
+        }
+      }
     }
     __syncthreads();
+    if (line >= o && line <= o + n) {
+      const int b0 = (line - o + 1) * PW + PL - o, b1 = b0 - PW;  // cell (line - o, nn - o) = b0 + nn
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        if (!kin_w(k)) continue;
+        const int nn = 4 * k + j;
+        const float2 x1 = buf[b0 + nn], x2 = buf[b1 + nn - 1], x3 = buf[b0 + nn - 1], x4 = buf[b1 + nn];
+        const float2 y1 = buf[PP + b0 + nn], y2 = buf[PP + b1 + nn - 1], y3 = buf[PP + b0 + nn - 1],
+                     y4 = buf[PP + b1 + nn];
+        // -(x1 + y1) + (x2 + y2) + (x3 - y3) - (x4 - y4)
+        f0[k].x = ((x2.x - x1.x) + (x3.x - x4.x)) + ((y2.x - y1.x) + (y4.x - y3.x));
+        f0[k].y = ((x2.y - x1.y) + (x3.y - x4.y)) + ((y2.y - y1.y) + (y4.y - y3.y));
+        if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);  // bound the reads in flight
+      }
+    }
+    meas_sums(buf + PW + PL, PW, true);
+    meas_sums(buf + PP + PW + PL, PW, false);
+    __syncthreads();
+  } else {
+    // x plane, then y plane, at buf[r * n + c]
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = t; i < plane; i += C::THREADS) {
+        const bool v = a.mask[i] != 0;
+        const float va = sa[pass * plane + i];
+        const float vb = sbb[pass * plane + i];
+        buf[i] = make_float2(v ? va : 0.f, v && hasB ? vb : 0.f);
+      }
+      __syncthreads();
+      const float sgn3 = pass == 0 ? 1.f : -1.f;  // r = s_x - s_y
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        if (!kin_w(k)) continue;  // no pupil cell touches these nodes
+        const uint32_t c = code_of(k);
+        const int nn = 4 * k + j;
+        const int nl = nn == 0 ? N - 1 : nn - 1;
+        float2 f = f0[k];
+        if (!(c & 1u)) { const float2 v = buf[(line - o) * n + (nn - o)]; f = csub(f, v); }
+        if (!(c & 2u)) { const float2 v = buf[(up - o) * n + (nl - o)]; f = cadd(f, v); }
+        if (!(c & 4u)) { const float2 v = buf[(line - o) * n + (nl - o)]; f.x = fmaf(sgn3, v.x, f.x); f.y = fmaf(sgn3, v.y, f.y); }
+        if (!(c & 8u)) { const float2 v = buf[(up - o) * n + (nn - o)]; f.x = fmaf(-sgn3, v.x, f.x); f.y = fmaf(-sgn3, v.y, f.y); }
+        f0[k] = f;
+      }
+      meas_sums(buf, n, pass == 0);
+      __syncthreads();
+    }
   }
+  // measured sums kept in registers: this line's R_m and the C_n of column t / 4
+  const float2 rmeas = sums[N + line], cmeas = sums[t >> 2];
   const bool in_rows = line >= o && line <= o + n;  // rows that can carry forcing
   if constexpr (C::F0_IN_LDS) {
     if (in_rows) {
@@ -243,18 +321,23 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   // ---- Fourier step: x holds q2 (row layout) on entry, phi on exit.  Row lines with
   // `fwd` false must hold zeros (they are written as such); with `inv` false the line's
   // phi is not computed.
-  // `loop` (a compile-time literal at each call): the transform of a window-supported q2
-  // whose result is needed on the window rows and one row either side.
+  // `mode` (a compile-time literal at each call) with WIN: 1 = the loop's transform of a
+  // window-supported q2 whose result is needed on the window rows and one row either
+  // side; 2 = the final one, whose input may also have the Eq. 5 rows 0 and N-1 and whose
+  // result is needed on the window rows; 0 = no pruning of the column pass.
   // The signed transforms leave lane signs on the spectra: the row pass's on the LDS
   // columns it writes, the column pass's on its own values; the filter tables carry both.
-  auto solve = [&](float2 *x, const float *h, bool fwd, bool inv, bool loop) {
+  auto solve = [&](float2 *x, const float *h, bool fwd, bool inv, int mode) {
     if (fwd) line_fft_fwd_s<T>(x, tw, j, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
     __syncthreads();
     float2 y[T];
 #pragma unroll
-    for (int k = 0; k < T; ++k) y[k] = loop && !kin_w(k) ? make_float2(0.f, 0.f) : buf[(4 * k + j) * P + line];
+    for (int k = 0; k < T; ++k) {
+      const bool zero = (mode == 1 && !kin_w(k)) || (mode == 2 && !kin_w(k) && k != 0 && k != T - 1);
+      y[k] = zero ? make_float2(0.f, 0.f) : buf[(4 * k + j) * P + col];
+    }
     line_fft_fwd_s<T>(y, tw, j, q);
     const float *ht = h + t * T;  // thread-contiguous: one address, immediate offsets
 #pragma unroll
@@ -266,7 +349,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     line_fft_inv_s<T>(y, twi, j, sj, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-      if (loop ? kin_r(k) : kin_w(k)) buf[(4 * k + j) * P + line] = y[k];
+      if (mode == 1 ? kin_r(k) : kin_w(k)) buf[(4 * k + j) * P + col] = y[k];
     }
     __syncthreads();
     if (inv) {
@@ -340,9 +423,12 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   //   node (0, n)   by -(C_n + C_{n-1}),   node (N-1, n) by +(C_n + C_{n-1}).
   // Outside the pupil the slopes are the model slopes of the periodic phase, whose
   // sums along a full row (x) or column (y) telescope to zero, so R_m and C_n are the
-  // sums of the in-pupil misfits (measured - model) alone.  When the step runs once
-  // (F0 is read for the last time here) the y misfits take the place of F0 (the
-  // thread's own LDS slots or registers); otherwise they are held in registers.
+  // sums of the in-pupil misfits (measured - model) alone: the measured sums from the
+  // set-up minus the model sums taken here.  When the step runs once (F0 is read for the
+  // last time here) the negated in-pupil y model slopes take the place of F0 (the
+  // thread's own LDS slots or registers); otherwise they are held in registers.  The
+  // measured slopes themselves are read again only for the residual or the written
+  // slopes.
   constexpr bool EY_IN_F0 = !EACH;
   auto final_step = [&](float2 *x, bool fix, bool write) -> bool {
 #pragma unroll
@@ -353,8 +439,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     const unsigned wrow = unsigned(line >= o && line < o + n ? line - o : 0) * unsigned(n);
     const size_t gplane = (size_t)N * N;
     float *ea = a.out + (size_t)fa * 2 * gplane;  // extended slopes of frame A (write mode)
-    float2 rowacc = make_float2(0.f, 0.f);
+    float2 rowacc = make_float2(0.f, 0.f);  // minus the in-pupil model x slopes of the row
     float ra = 0.f, rb = 0.f, na = 0.f, nb = 0.f;  // in-pupil misfit and measurement energy
+    const bool need_meas = want_resid || write;
     float2 DY[EY_IN_F0 ? 1 : T];
     if (row_w) {  // (pruned: the other lines have no pupil cell and q2 = 0 there)
 #pragma unroll
@@ -367,10 +454,6 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         const uint32_t c4 = code_of(k);
         const bool meas = !(c4 & 1u);
         const unsigned widx = wrow + unsigned(nn >= o && nn < o + n ? nn - o : 0);
-        // measured slopes, exactly zero outside the pupil (whatever the input holds there)
-        const float mxa = select_bits(meas, sa[widx], 0.f), mya = select_bits(meas, sa[uplane + widx], 0.f);
-        const float mxb = select_bits(meas, sbb[widx] * bflag, 0.f);
-        const float myb = select_bits(meas, sbb[uplane + widx] * bflag, 0.f);
         const int sp = slot_p(k), sm = slot_m(k);
         const float2 ph = x[k];
         const float2 b = buf[line * P + sp];       // (m, n+1)
@@ -379,24 +462,34 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         // cell (m, n): s_x = (b - a + d - c) / 2, s_y = (c - a + d - b) / 2
         const float2 gx = make_float2(0.5f * ((b.x - ph.x) + (d1.x - c.x)), 0.5f * ((b.y - ph.y) + (d1.y - c.y)));
         const float2 gy = make_float2(0.5f * ((c.x - ph.x) + (d1.x - b.x)), 0.5f * ((c.y - ph.y) + (d1.y - b.y)));
-        const float2 ex = make_float2(select_bits(meas, mxa - gx.x, 0.f), select_bits(meas, mxb - gx.y, 0.f));
-        const float2 ey = make_float2(select_bits(meas, mya - gy.x, 0.f), select_bits(meas, myb - gy.y, 0.f));
-        if (want_resid) {
-          ra = fmaf(ex.x, ex.x, fmaf(ey.x, ey.x, ra));
-          rb = fmaf(ex.y, ex.y, fmaf(ey.y, ey.y, rb));
-          na = fmaf(mxa, mxa, fmaf(mya, mya, na));
-          nb = fmaf(mxb, mxb, fmaf(myb, myb, nb));
-        }
-        rowacc = cadd(rowacc, ex);
-        if (write && active) {
-          const size_t idx = (size_t)line * N + nn;
-          ea[idx] = select_bits(meas, mxa, gx.x);
-          ea[gplane + idx] = select_bits(meas, mya, gy.x);
-          if (hasB) {
-            ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
-            ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
+        // minus the in-pupil model slopes (exactly zero outside the pupil)
+        const float2 mgx = make_float2(select_bits(meas, -gx.x, 0.f), select_bits(meas, -gx.y, 0.f));
+        const float2 mgy = make_float2(select_bits(meas, -gy.x, 0.f), select_bits(meas, -gy.y, 0.f));
+        rowacc = cadd(rowacc, mgx);
+        if (need_meas) {
+          // measured slopes, exactly zero outside the pupil (whatever the input holds there)
+          const float mxa = select_bits(meas, sa[widx], 0.f), mya = select_bits(meas, sa[uplane + widx], 0.f);
+          const float mxb = select_bits(meas, sbb[widx] * bflag, 0.f);
+          const float myb = select_bits(meas, sbb[uplane + widx] * bflag, 0.f);
+          if (want_resid) {
+            const float2 ex = make_float2(select_bits(meas, mxa - gx.x, 0.f), select_bits(meas, mxb - gx.y, 0.f));
+            const float2 ey = make_float2(select_bits(meas, mya - gy.x, 0.f), select_bits(meas, myb - gy.y, 0.f));
+            ra = fmaf(ex.x, ex.x, fmaf(ey.x, ey.x, ra));
+            rb = fmaf(ex.y, ex.y, fmaf(ey.y, ey.y, rb));
+            na = fmaf(mxa, mxa, fmaf(mya, mya, na));
+            nb = fmaf(mxb, mxb, fmaf(myb, myb, nb));
           }
-        } else {
+          if (write && active) {
+            const size_t idx = (size_t)line * N + nn;
+            ea[idx] = select_bits(meas, mxa, gx.x);
+            ea[gplane + idx] = select_bits(meas, mya, gy.x);
+            if (hasB) {
+              ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
+              ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
+            }
+          }
+        }
+        if (!write) {
           const float2 d2 = buf[up * P + sm];  // (m-1, n-1)
           const float2 d3 = buf[dn * P + sm];  // (m+1, n-1)
           const float2 d4 = buf[up * P + sp];  // (m-1, n+1)
@@ -411,11 +504,11 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         clip_w(x[k], k);
         }
         if constexpr (EY_IN_F0 && C::F0_IN_LDS) {
-          if (in_rows) f0rows[f0row + k] = ey;  // after this thread's last read of the slot
+          if (in_rows) f0rows[f0row + k] = mgy;  // after this thread's last read of the slot
         } else if constexpr (EY_IN_F0) {
-          f0[k] = ey;
+          f0[k] = mgy;
         } else {
-          DY[k] = ey;
+          DY[k] = mgy;
         }
         if ((k & 1) == 1) __builtin_amdgcn_sched_barrier(0);
       }
@@ -465,14 +558,19 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
 #pragma unroll
         for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = EY_IN_F0 ? f0[k] : DY[k];
       }
-      if (j == 0) sums[N + line] = rowacc;
+      if (j == 0) sums[N + line] = cadd(rmeas, rowacc);
       __syncthreads();
-      if (t < N) {  // C_n over the pupil rows, in a fixed order (deterministic)
+      {  // C_n over the pupil rows: four lanes per column, fixed order (deterministic)
+        const int nn = t >> 2, jj = t & 3;
+        const int slot = T * (nn & 3) + (nn >> 2);
         float2 cs = make_float2(0.f, 0.f);
-        const int slot = T * (t & 3) + (t >> 2);
-        for (int r = 0; r < n; ++r)
+        for (int r = jj; r < n; r += 4)
           cs = cadd(cs, EY_IN_F0 && C::F0_IN_LDS ? f0rows[r * P + slot] : buf[(o + r) * P + slot]);
-        sums[t] = cs;
+        cs.x += dpp_xor1(cs.x);
+        cs.y += dpp_xor1(cs.y);
+        cs.x += dpp_xor2(cs.x);
+        cs.y += dpp_xor2(cs.y);
+        if (jj == 0) sums[nn] = cadd(cmeas, cs);
       }
       __syncthreads();
       const float2 Rm = sums[N + line], Rm1 = sums[N + up];
@@ -557,7 +655,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   }
 
   for (int it = 0; it < a.n_iter; ++it) {
-    solve(x, a.h_loop, row_w, row_r1, WIN);
+    solve(x, a.h_loop, row_w, row_r1, WIN ? 1 : 0);
     if (it == a.n_iter - 1) break;
     if constexpr (EACH) final_step(x, true, false);
     else stencil(x);
@@ -572,7 +670,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     stencil(x);
   }
   // the output is the window rows; with Eq. 5 the border rows 0 and N-1 carry forcing
-  solve(x, a.h_final, row_w || (fix_final && (line == 0 || line == N - 1)), row_w, false);
+  solve(x, a.h_final, row_w || (fix_final && (line == 0 || line == N - 1)), row_w, WIN ? 2 : 0);
 
   // (n+1) x (n+1) node window
   if (active && line >= o && line <= o + n) {

@@ -20,6 +20,7 @@ struct OnchipArgs {
                           // bit 2: cell (m, n-1), bit 3: cell (m-1, n)
   const float *start;     // optional [B][2][N][N]: out-of-pupil start slopes (NULL: zeros)
   float *resid;           // optional [B]: in-pupil misfit of the last iteration
+  const uint8_t *mask;    // [n][n]: 1 = valid subaperture
   int B, n, o, n_iter, flags;
 };
 
