@@ -12,6 +12,15 @@
 // and, once per call, the explicit final step (cell slopes, Eq. 5 sums and
 // fix, scatter to q) and the output kernels.
 //
+// Without per-iteration Eq. 5 the loop is pruned to the window, as in the on-chip
+// kernel: q2 vanishes outside the n+1 window rows (it is G^T of slopes that differ from
+// the model slopes of phi only inside the pupil, and phi came from the previous q2), so
+// row_fwd runs on the blocks of the window rows (zeros elsewhere in them), col reads only
+// the window rows and writes back only the rows the next pass needs, and row_inv runs on
+// the blocks of the window rows and one row either side.  The last solve before an
+// explicit final step writes all rows (phi is exact everywhere; only its rows were
+// skipped).
+//
 // FFT of a 256-point line: 16 threads, 16 x 16 decomposition through LDS.
 // Stage A: thread r takes points 16a + r, DFT-16 over a, twiddle W_256^(r k1);
 // stage B: thread k1 takes the 16 contiguous results, DFT-16.  Position
@@ -93,7 +102,8 @@ __device__ __forceinline__ void measured(const MPArgs &a, int pair, int cm, int 
 // ---------------------------------------------------------------- row phase
 // mode 0: q2 = F0 (start of the loop; also stores F0 rows of the window)
 // mode 1: q2 = F0 + sum over out-of-pupil cells of (phi - phi_diagonal)
-__global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
+// blocks start at row block b0
+__global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, int b0) {
   // phi rows m0-1 .. m0+16; once the stencil has read them, the same LDS holds the 16
   // padded lines of the row transforms (R * LP <= (R + 2) * NN), so four blocks fit a CU
   __shared__ float2 ph[(R + 2) * NN];
@@ -101,7 +111,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
   float2 *const L = ph;
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
-  const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl;
+  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R, m = m0 + rl;
   load_tw(tw, a.tw256, t);
   if (mode == 1) {
     const float2 *P = a.phi + field(pair);
@@ -128,8 +138,8 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
         F0[(size_t)(m - a.o) * NN + nn] = f;
       }
-    } else {
-      if (win_row) f = F0[(size_t)(m - a.o) * NN + nn];
+    } else if (win_row) {  // (q2 = 0 on the other rows)
+      f = F0[(size_t)(m - a.o) * NN + nn];
       const uint8_t c = a.codes[m * NN + nn];
       const float2 p0 = ph[(rl + 1) * NN + nn];
       const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
@@ -158,7 +168,8 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode) {
 }
 
 // ---------------------------------------------------------------- column phase
-__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h) {
+// rows outside [rlo, rhi] are read as zeros; only rows in [wlo, whi] are written back
+__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, int rlo, int rhi, int wlo, int whi) {
   __shared__ float2 L[R * LP];
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, cl = t >> 4, r = t & 15;
@@ -167,7 +178,7 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h) 
   float2 *S = a.spec + field(pair);
   for (int i = t; i < R * NN; i += THREADS) {
     const int row = i / R, cc = i % R;
-    L[cc * LP + pad(row)] = S[(size_t)row * NN + c0 + cc];
+    L[cc * LP + pad(row)] = row >= rlo && row <= rhi ? S[(size_t)row * NN + c0 + cc] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   fft_stage_a<-1>(L + cl * LP, r, tw);
@@ -189,16 +200,16 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h) 
   __syncthreads();
   for (int i = t; i < R * NN; i += THREADS) {
     const int row = i / R, cc = i % R;
-    S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
+    if (row >= wlo && row <= whi) S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
   }
 }
 
 // ---------------------------------------------------------------- inverse rows
-__global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a) {
+__global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
   __shared__ float2 L[R * LP];
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
-  const int pair = blockIdx.y, m0 = blockIdx.x * R;
+  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
   load_tw(tw, a.tw256, t);
   const float2 *S = a.spec + field(pair);
   for (int i = t; i < R * NN; i += THREADS) {
@@ -347,23 +358,38 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   const bool each = (a.flags & kMPPeriodicEach) != 0;
   const bool explicit_final = periodic || extend || (each && a.n_iter > 0);
   const bool fix_final = periodic || (each && a.n_iter > 0);
+  // window rows [o, o+n] and the stencil's reach [o-1, o+n+1]; their row blocks
+  // (with o = 1 the reach wraps around: every row)
+  const int wlo = a.o, whi = a.o + a.n;
+  const int rlo = a.o >= 2 ? a.o - 1 : 0, rhi = a.o >= 2 ? a.o + a.n + 1 : NN - 1;
+  const int wb0 = wlo / R, wb1 = whi / R, rb0 = rlo / R, rb1 = rhi / R;
+  const dim3 wrows(wb1 - wb0 + 1, pairs), rrows(rb1 - rb0 + 1, pairs);
   auto explicit_q = [&](bool phi_zero, bool fix) {
     hipLaunchKernelGGL(slopes_kernel, rows, blk, 0, s, a, phi_zero ? 1 : 0);
     if (fix) hipLaunchKernelGGL(periodic_kernel, dim3(pairs), blk, 0, s, a);
   };
-  // start: q2 = F0 (also fills the F0 rows), forward row FFTs
-  hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 0);
+  // start: q2 = F0 (also fills the F0 rows), forward row FFTs of the window rows
+  hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 0, wb0);
   for (int it = 0; it < a.n_iter; ++it) {
-    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_loop);
-    hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
-    if (it == a.n_iter - 1) break;
+    const bool last = it == a.n_iter - 1;
+    // q2 is window-supported here unless per-iteration Eq. 5 made it explicit
+    const bool win_in = !each || it == 0;
+    const bool full_out = each || (last && explicit_final);  // phi needed on every row
+    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
+                       full_out ? 0 : rlo, full_out ? NN - 1 : rhi);
+    if (full_out)
+      hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
+    else
+      hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0);
+    if (last) break;
     if (each) {
       explicit_q(false, true);
       hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
     } else {
-      hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 1);
+      hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0);
     }
   }
+  bool win_final = true;  // q2 of the final solve window-supported
   if (explicit_final) {
     explicit_q(a.n_iter == 0, fix_final);
     if (extend) {
@@ -371,11 +397,13 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
       return hipGetLastError();
     }
     hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
+    win_final = false;
   } else if (a.n_iter > 0) {
-    hipLaunchKernelGGL(row_fwd_kernel, rows, blk, 0, s, a, 1);
+    hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0);
   }
-  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final);
-  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
+  // the output is the window rows
+  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo, whi);
+  hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0);
   hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);
   return hipGetLastError();
 }
@@ -514,7 +542,7 @@ hipError_t multipass_generate(const MPArgs &a, const GenArgs &g, hipStream_t s) 
   const dim3 rows(NN / R, pairs), blk(THREADS);
   hipLaunchKernelGGL(gen_spectrum_kernel, rows, blk, 0, s, a, g);
   hipLaunchKernelGGL(col_inv_kernel, rows, blk, 0, s, a);
-  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a);
+  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
   hipLaunchKernelGGL(gen_slopes_kernel, dim3(16, pairs), blk, 0, s, a, g);
   if (g.d_counter) hipLaunchKernelGGL(mp_counter_add_kernel, dim3(1), dim3(64), 0, s, g.d_counter, uint64_t(2 * pairs));
   return hipGetLastError();
