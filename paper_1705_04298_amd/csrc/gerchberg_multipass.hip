@@ -115,7 +115,9 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
   load_tw(tw, a.tw256, t);
   if (mode == 1) {
     const float2 *P = a.phi + field(pair);
-    for (int i = t; i < (R + 2) * NN; i += THREADS) {
+#pragma unroll
+    for (int c_ = 0; c_ < (R + 2) * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+      const int i = t + c_ * THREADS;
       const int row = (m0 - 1 + i / NN) & (NN - 1);
       ph[i] = P[(size_t)row * NN + (i % NN)];
     }
@@ -161,7 +163,9 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
   fft_stage_b<-1>(L + rl * LP, r);
   __syncthreads();
   float2 *S = a.spec + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
     S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
   }
@@ -176,9 +180,24 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
   const int pair = blockIdx.y, c0 = blockIdx.x * R;
   load_tw(tw, a.tw256, t);
   float2 *S = a.spec + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
-    const int row = i / R, cc = i % R;
-    L[cc * LP + pad(row)] = row >= rlo && row <= rhi ? S[(size_t)row * NN + c0 + cc] : make_float2(0.f, 0.f);
+  // rows outside [rlo, rhi] load row rlo (a cache hit) and are replaced by zeros: every
+  // load is issued first and kept unconditional, so that they are not serialised behind
+  // divergent branches
+  constexpr int NL = R * NN / THREADS;
+  float2 v[NL];
+#pragma unroll
+  for (int c_ = 0; c_ < NL; ++c_) {
+    const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
+    const bool in = row >= rlo && row <= rhi;
+    v[c_] = S[(size_t)(in ? row : rlo) * NN + c0 + cc];
+  }
+#pragma unroll
+  for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
+#pragma unroll
+  for (int c_ = 0; c_ < NL; ++c_) {
+    const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
+    const bool in = row >= rlo && row <= rhi;
+    L[cc * LP + pad(row)] = in ? v[c_] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   fft_stage_a<-1>(L + cl * LP, r, tw);
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
   fft_stage_b<-1>(L + cl * LP, r);
   __syncthreads();
   const float *hc = h + (size_t)(c0 + cl) * NN;
-#pragma unroll 4
+#pragma unroll
   for (int q = 0; q < R; ++q) {
     const int p = r + R * q;
     float2 v = L[cl * LP + pad(p)];
@@ -198,7 +217,9 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
   __syncthreads();
   fft_stage_a<+1>(L + cl * LP, r, tw);
   __syncthreads();
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / R, cc = i % R;
     if (row >= wlo && row <= whi) S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
   }
@@ -212,7 +233,9 @@ __global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
   const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
   load_tw(tw, a.tw256, t);
   const float2 *S = a.spec + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
     L[row * LP + pad(p)] = S[(size_t)(m0 + row) * NN + p];
   }
@@ -222,7 +245,9 @@ __global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
   fft_stage_a<+1>(L + rl * LP, r, tw);
   __syncthreads();
   float2 *Ph = a.phi + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
     Ph[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
   }
@@ -236,7 +261,9 @@ __global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero)
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl;
   const float2 *P = a.phi + field(pair);
-  for (int i = t; i < (R + 1) * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < (R + 1) * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = (m0 + i / NN) & (NN - 1);
     ph[i] = phi_zero ? make_float2(0.f, 0.f) : P[(size_t)row * NN + (i % NN)];
   }
@@ -318,7 +345,9 @@ __global__ __launch_bounds__(THREADS) void scatter_kernel(MPArgs a) {
   fft_stage_b<-1>(L + rl * LP, r);
   __syncthreads();
   float2 *S = a.spec + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
     S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
   }
@@ -478,7 +507,9 @@ __global__ __launch_bounds__(THREADS) void col_inv_kernel(MPArgs a) {
   const int pair = blockIdx.y, c0 = blockIdx.x * R;
   load_tw(tw, a.tw256, t);
   float2 *S = a.spec + field(pair);
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / R, cc = i % R;
     L[cc * LP + pad(row)] = S[(size_t)row * NN + c0 + cc];
   }
@@ -487,7 +518,9 @@ __global__ __launch_bounds__(THREADS) void col_inv_kernel(MPArgs a) {
   __syncthreads();
   fft_stage_a<+1>(L + cl * LP, r, tw);
   __syncthreads();
-  for (int i = t; i < R * NN; i += THREADS) {
+#pragma unroll
+  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
     const int row = i / R, cc = i % R;
     S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
   }
