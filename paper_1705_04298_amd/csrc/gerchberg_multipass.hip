@@ -26,7 +26,7 @@
 // stage B: thread k1 takes the 16 contiguous results, DFT-16.  Position
 // 16 k1 + k2 then holds frequency k1 + 16 k2 (digit-reversed); the filter
 // table is laid out in that order and the inverse undoes it.  Lines are
-// padded by one element every 16 (272 per line) to spread LDS banks.
+// padded by one element every 16, plus one (273 per line), to spread LDS banks.
 #include "fft_lane.h"
 #include "multipass.h"
 
@@ -36,7 +36,8 @@ namespace mp {
 
 constexpr int NN = 256;
 constexpr int R = 16;
-constexpr int LP = NN + NN / R;  // padded line length (complex)
+constexpr int LP = NN + NN / R + 1;  // padded line length (complex); odd, so that the column
+                                     // pass's transposing copies spread over the LDS banks
 constexpr int THREADS = 256;
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
