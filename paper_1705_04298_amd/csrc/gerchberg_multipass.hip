@@ -123,9 +123,21 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
       ph[i] = P[(size_t)row * NN + (i % NN)];
     }
   }
-  __syncthreads();
   const bool win_row = m >= a.o && m <= a.o + a.n;
   float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
+  // the forcing and the node codes of this thread's nodes, loaded with the phi rows (from
+  // a valid row on the lines outside the window, whose result is replaced by zero)
+  float2 f0v[R];
+  uint32_t cv[R];
+  if (mode == 1) {
+    const size_t fr = (size_t)(win_row ? m - a.o : 0) * NN;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      f0v[q] = F0[fr + r + R * q];
+      cv[q] = a.codes[m * NN + r + R * q];
+    }
+  }
+  __syncthreads();
   float2 fq[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -141,9 +153,9 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
         F0[(size_t)(m - a.o) * NN + nn] = f;
       }
-    } else if (win_row) {  // (q2 = 0 on the other rows)
-      f = F0[(size_t)(m - a.o) * NN + nn];
-      const uint8_t c = a.codes[m * NN + nn];
+    } else {
+      f = f0v[q];
+      const uint32_t c = cv[q];
       const float2 p0 = ph[(rl + 1) * NN + nn];
       const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
       const float2 d1 = ph[(rl + 2) * NN + np], d2 = ph[rl * NN + nm];
@@ -152,6 +164,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
       if (c & 2) f = cadd(f, csub(p0, d2));
       if (c & 4) f = cadd(f, csub(p0, d3));
       if (c & 8) f = cadd(f, csub(p0, d4));
+      if (!win_row) f = make_float2(0.f, 0.f);  // (q2 = 0 on the other rows)
     }
     fq[q] = f;
   }
