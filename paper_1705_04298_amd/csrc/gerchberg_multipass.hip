@@ -281,19 +281,36 @@ __global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero)
     const int row = (m0 + i / NN) & (NN - 1);
     ph[i] = phi_zero ? make_float2(0.f, 0.f) : P[(size_t)row * NN + (i % NN)];
   }
+  // the measured slopes and the mask of this thread's cells, loaded with the phi rows and
+  // unconditionally (cells outside the window read cell 0 and are not used)
+  const int n = a.n, o = a.o, plane = n * n;
+  const float *sa = a.slopes + (size_t)(2 * pair) * 2 * plane;
+  const bool hasB = 2 * pair + 1 < a.B;
+  const float *sb = hasB ? sa + 2 * plane : sa;
+  float2 mx[R], my[R];
+  bool inp[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q;
+    const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
+    const int idx = inw ? (m - o) * n + (nn - o) : 0;
+    inp[q] = inw && a.mask[idx] != 0;
+    mx[q] = make_float2(sa[idx], sb[idx]);
+    my[q] = make_float2(sa[plane + idx], sb[plane + idx]);
+  }
   __syncthreads();
   float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
   float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
   for (int q = 0; q < R; ++q) {
     const int nn = r + R * q, np = (nn + 1) & (NN - 1);
-    float2 sx, sy;
-    if (in_pupil(a.mask, a.n, a.o, m, nn)) {
-      measured(a, pair, m, nn, sx, sy);
-    } else {
-      const float2 a0 = ph[rl * NN + nn], b = ph[rl * NN + np];
-      const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
-      sx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
-      sy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
+    const float2 a0 = ph[rl * NN + nn], b = ph[rl * NN + np];
+    const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
+    float2 sx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
+    float2 sy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
+    if (inp[q]) {  // measured inside the pupil (bit for bit), G phi outside
+      sx = make_float2(mx[q].x, hasB ? mx[q].y : 0.f);
+      sy = make_float2(my[q].x, hasB ? my[q].y : 0.f);
     }
     SX[(size_t)m * NN + nn] = sx;
     SY[(size_t)m * NN + nn] = sy;
@@ -314,6 +331,7 @@ __global__ __launch_bounds__(THREADS) void periodic_kernel(MPArgs a) {
   float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
   float2 *sums = a.sums + (size_t)pair * 2 * NN;
   float2 cs = make_float2(0.f, 0.f);
+#pragma unroll 32
   for (int m = 0; m < NN; ++m) cs = cadd(cs, SY[(size_t)m * NN + t]);
   __syncthreads();  // all column reads done before row N-1 changes
   SY[(size_t)(NN - 1) * NN + t] = csub(SY[(size_t)(NN - 1) * NN + t], cs);
