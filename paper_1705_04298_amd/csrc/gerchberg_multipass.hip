@@ -103,8 +103,15 @@ __device__ __forceinline__ void measured(const MPArgs &a, int pair, int cm, int 
 // ---------------------------------------------------------------- row phase
 // mode 0: q2 = F0 (start of the loop; also stores F0 rows of the window)
 // mode 1: q2 = F0 + sum over out-of-pupil cells of (phi - phi_diagonal)
+// mode 2: mode 1 plus Eq. 5 on the border node columns of the window rows:
+//         node (m, 0) by -(R_m + R_{m-1}), node (m, N-1) by +(R_m + R_{m-1})
+// mode 3: Eq. 5 on the border node rows: node (0, n) by -(C_n + C_{n-1}), node (N-1, n) by
+//         +(C_n + C_{n-1}); row blocks 0 and N/16 - 1, only rows 0 and N-1 are written.  A
+//         mode-2 launch runs it on its last two blocks (after the nw window blocks; nw is also
+//         the number of column-sum partials).
+// R_m = sums[N + m] and the column-sum partials come from eq5_kernel.
 // blocks start at row block b0
-__global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, int b0) {
+__global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg, int b0, int nw) {
   // phi rows m0-1 .. m0+16; once the stencil has read them, the same LDS holds the 16
   // padded lines of the row transforms (R * LP <= (R + 2) * NN), so four blocks fit a CU
   __shared__ float2 ph[(R + 2) * NN];
@@ -112,9 +119,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
   float2 *const L = ph;
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
-  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R, m = m0 + rl;
+  const int mode = mode_arg == 2 && int(blockIdx.x) >= nw ? 3 : mode_arg;  // uniform per block
+  const int pair = blockIdx.y, m0 = mode == 3 ? (int(blockIdx.x) == nw ? 0 : NN - R) : (blockIdx.x + b0) * R;
+  const int m = m0 + rl;
   load_tw(tw, a.tw256, t);
-  if (mode == 1) {
+  if (mode == 1 || mode == 2) {
     const float2 *P = a.phi + field(pair);
 #pragma unroll
     for (int c_ = 0; c_ < (R + 2) * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
   // a valid row on the lines outside the window, whose result is replaced by zero)
   float2 f0v[R];
   uint32_t cv[R];
-  if (mode == 1) {
+  if (mode == 1 || mode == 2) {
     const size_t fr = (size_t)(win_row ? m - a.o : 0) * NN;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
         F0[(size_t)(m - a.o) * NN + nn] = f;
       }
-    } else {
+    } else if (mode != 3) {
       f = f0v[q];
       const uint32_t c = cv[q];
       const float2 p0 = ph[(rl + 1) * NN + nn];
@@ -165,8 +174,35 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
       if (c & 4) f = cadd(f, csub(p0, d3));
       if (c & 8) f = cadd(f, csub(p0, d4));
       if (!win_row) f = make_float2(0.f, 0.f);  // (q2 = 0 on the other rows)
+      if (mode == 2 && win_row && (nn == 0 || nn == NN - 1)) {
+        const float2 *Rs = a.sums + (size_t)pair * 2 * NN + NN;
+        const float2 r0 = m <= a.o + a.n - 1 ? Rs[m] : make_float2(0.f, 0.f);
+        const float2 r1 = m - 1 >= a.o ? Rs[m - 1] : make_float2(0.f, 0.f);
+        const float2 rr = cadd(r0, r1);
+        f = nn == 0 ? csub(f, rr) : cadd(f, rr);
+      }
     }
     fq[q] = f;
+  }
+  if (mode == 3) {  // (q2 = 0 on the block's other rows)
+    // C_n for n = t from the b0 <= N/16 partials (fixed order, loads issued together), staged in
+    // the phi-row LDS that this mode does not use
+    const float2 *part = a.sx + field(pair);  // column-sum partials [nw][N]
+    float2 pv[NN / R];
+#pragma unroll
+    for (int b = 0; b < NN / R; ++b) pv[b] = part[(b < nw ? b : 0) * NN + t];
+    float2 cn = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < NN / R; ++b)
+      if (b < nw) cn = cadd(cn, pv[b]);
+    ph[t] = cn;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int nn = r + R * q, nl = (nn - 1) & (NN - 1);
+      const float2 cc = cadd(ph[nn], ph[nl]);
+      fq[q] = m == 0 ? make_float2(-cc.x, -cc.y) : (m == NN - 1 ? cc : make_float2(0.f, 0.f));
+    }
   }
   __syncthreads();  // every stencil read of the phi rows is done
 #pragma unroll
@@ -181,13 +217,78 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode, in
   for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
     const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
-    S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+    // rows 0 and N-1 belong to the border blocks of a mode-2 launch (never window rows)
+    const bool border_row = m0 + row == 0 || m0 + row == NN - 1;
+    if (mode == 3 ? border_row : !(mode_arg == 2 && border_row)) S[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
   }
 }
 
+// Eq. 5 sums from the in-pupil misfits (measured - model slopes of phi), on the window's row
+// blocks: R_m (fixed-order row sums) to sums[N + m] for every row of the block, and the
+// block's partial column sums of the y misfits to the column-sum partials [block][N] (kept in
+// the s_x field, unused on this path).  Outside the pupil the slopes are the model slopes of
+// the periodic phase, whose full-row (x) and full-column (y) sums vanish, so R_m and C_n are
+// these misfit sums alone.
+__global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
+  __shared__ float2 ph[(R + 1) * NN];
+  __shared__ float2 part[THREADS];
+  __shared__ float2 eyl[R * NN];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R, m = m0 + rl;
+  const float2 *P = a.phi + field(pair);
+#pragma unroll
+  for (int c_ = 0; c_ < (R + 1) * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * THREADS;
+    const int row = (m0 + i / NN) & (NN - 1);
+    ph[i] = P[(size_t)row * NN + (i % NN)];
+  }
+  const int n = a.n, o = a.o, plane = n * n;
+  const float *sa = a.slopes + (size_t)(2 * pair) * 2 * plane;
+  const bool hasB = 2 * pair + 1 < a.B;
+  const float *sb = hasB ? sa + 2 * plane : sa;
+  float2 mx[R], my[R];
+  bool inp[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q;
+    const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
+    const int idx = inw ? (m - o) * n + (nn - o) : 0;
+    inp[q] = inw && a.mask[idx] != 0;
+    mx[q] = make_float2(sa[idx], hasB ? sb[idx] : 0.f);
+    my[q] = make_float2(sa[plane + idx], hasB ? sb[plane + idx] : 0.f);
+  }
+  __syncthreads();
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q, np = (nn + 1) & (NN - 1);
+    const float2 a0 = ph[rl * NN + nn], b = ph[rl * NN + np];
+    const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
+    const float2 gx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
+    const float2 gy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
+    const float2 ex = inp[q] ? csub(mx[q], gx) : make_float2(0.f, 0.f);
+    const float2 ey = inp[q] ? csub(my[q], gy) : make_float2(0.f, 0.f);
+    acc = cadd(acc, ex);
+    eyl[rl * NN + nn] = ey;
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (r == 0) {  // fixed-order row sum
+    float2 s2 = make_float2(0.f, 0.f);
+    for (int i = 0; i < R; ++i) s2 = cadd(s2, part[rl * R + i]);
+    a.sums[(size_t)pair * 2 * NN + NN + m] = s2;
+  }
+  float2 cs = make_float2(0.f, 0.f);  // column t over the block's rows, fixed order
+#pragma unroll
+  for (int i = 0; i < R; ++i) cs = cadd(cs, eyl[i * NN + t]);
+  (a.sx + field(pair))[(size_t)blockIdx.x * NN + t] = cs;
+}
+
 // ---------------------------------------------------------------- column phase
-// rows outside [rlo, rhi] are read as zeros; only rows in [wlo, whi] are written back
-__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, int rlo, int rhi, int wlo, int whi) {
+// rows outside [rlo, rhi] (and, with `border`, other than 0 and N-1) are read as zeros;
+// only rows in [wlo, whi] are written back
+__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, int rlo, int rhi, int wlo, int whi,
+                                                      int border) {
   __shared__ float2 L[R * LP];
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, cl = t >> 4, r = t & 15;
@@ -202,7 +303,7 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) {
     const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
-    const bool in = row >= rlo && row <= rhi;
+    const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
     v[c_] = S[(size_t)(in ? row : rlo) * NN + c0 + cc];
   }
 #pragma unroll
@@ -210,7 +311,7 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) {
     const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
-    const bool in = row >= rlo && row <= rhi;
+    const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
     L[cc * LP + pad(row)] = in ? v[c_] : make_float2(0.f, 0.f);
   }
   __syncthreads();
@@ -419,6 +520,8 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   const bool each = (a.flags & kMPPeriodicEach) != 0;
   const bool explicit_final = periodic || extend || (each && a.n_iter > 0);
   const bool fix_final = periodic || (each && a.n_iter > 0);
+  // Eq. 5 after the loop from the in-pupil misfits, without full slope fields
+  const bool eq5_sums = periodic && !extend && !each && a.n_iter > 0;
   // window rows [o, o+n] and the stencil's reach [o-1, o+n+1]; their row blocks
   // (with o = 1 the reach wraps around: every row)
   const int wlo = a.o, whi = a.o + a.n;
@@ -430,14 +533,14 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     if (fix) hipLaunchKernelGGL(periodic_kernel, dim3(pairs), blk, 0, s, a);
   };
   // start: q2 = F0 (also fills the F0 rows), forward row FFTs of the window rows
-  hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 0, wb0);
+  hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 0, wb0, 0);
   for (int it = 0; it < a.n_iter; ++it) {
     const bool last = it == a.n_iter - 1;
     // q2 is window-supported here unless per-iteration Eq. 5 made it explicit
     const bool win_in = !each || it == 0;
-    const bool full_out = each || (last && explicit_final);  // phi needed on every row
+    const bool full_out = each || (last && explicit_final && !eq5_sums);  // phi needed on every row
     hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
-                       full_out ? 0 : rlo, full_out ? NN - 1 : rhi);
+                       full_out ? 0 : rlo, full_out ? NN - 1 : rhi, 0);
     if (full_out)
       hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
     else
@@ -447,11 +550,17 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
       explicit_q(false, true);
       hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
     } else {
-      hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0);
+      hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0, 0);
     }
   }
-  bool win_final = true;  // q2 of the final solve window-supported
-  if (explicit_final) {
+  bool win_final = true;  // q2 of the final solve window-supported (plus rows 0 and N-1 with Eq. 5)
+  bool border = false;
+  if (eq5_sums) {
+    hipLaunchKernelGGL(eq5_kernel, wrows, blk, 0, s, a, wb0);
+    // the window blocks (mode 2) and the two border-row blocks (mode 3) in one launch
+    hipLaunchKernelGGL(row_fwd_kernel, dim3(wb1 - wb0 + 3, pairs), blk, 0, s, a, 2, wb0, wb1 - wb0 + 1);
+    border = true;
+  } else if (explicit_final) {
     explicit_q(a.n_iter == 0, fix_final);
     if (extend) {
       hipLaunchKernelGGL(ext_out_kernel, dim3(NN, pairs), blk, 0, s, a);
@@ -460,10 +569,11 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
     win_final = false;
   } else if (a.n_iter > 0) {
-    hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0);
+    hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0, 0);
   }
   // the output is the window rows
-  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo, whi);
+  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
+                     whi, border ? 1 : 0);
   hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0);
   hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);
   return hipGetLastError();
