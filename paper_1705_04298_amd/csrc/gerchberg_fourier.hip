@@ -71,11 +71,25 @@ void fourier_kernel(FourierArgs a) {
 
   // measured slopes of the window rows, lane-blocked: grid column c -> slot T (c % 4) + c / 4
   const float *sf = a.slopes + (size_t)f * 2 * plane;
-  for (int i = t; i < n * N; i += TH) {
-    const int r = i / N, c = i - r * N;
-    float2 v = make_float2(0.f, 0.f);
-    if (c >= o && c < o + n) v = make_float2(sf[r * n + c - o], sf[plane + r * n + c - o]);
-    meas[r * P + T * (c & 3) + (c >> 2)] = v;
+  // all loads of a chunk are issued before its LDS stores (cells outside the window read
+  // cell 0 and are replaced by zeros): one memory latency per chunk, not per element
+  constexpr int CH = (N / 2 * N + TH - 1) / TH;
+  for (int i0 = t; i0 < n * N; i0 += CH * TH) {
+    float vx[CH], vy[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u * TH, r = i / N, c = i - r * N;
+      const bool in = i < n * N && c >= o && c < o + n;
+      const int g = in ? r * n + c - o : 0;
+      vx[u] = sf[g];
+      vy[u] = sf[plane + g];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u * TH, r = i / N, c = i - r * N;
+      const bool in = i < n * N && c >= o && c < o + n;
+      if (i < n * N) meas[r * P + T * (c & 3) + (c >> 2)] = in ? make_float2(vx[u], vy[u]) : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   const uint32_t pup = a.inpupil[t];
