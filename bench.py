@@ -79,8 +79,20 @@ def cpu_baseline(slopes: np.ndarray, workers: int, sample: int):
     ref = {i: ph for part in res for i, ph in part}
     rec = {"value": len(ref) / dt, "unit": "frames/s", "cores": workers, "kind": "oracle",
            "sample": f"first {sample} frames of the benchmark batch, FP64 NumPy oracle, "
-                     f"{workers} single-threaded worker processes, {dt:.1f} s wall"}
+                     f"{workers} single-threaded worker processes, {dt:.1f} s wall",
+           "cpu_model": cpu_model()}
     return rec, ref
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def kernel_fingerprint() -> str:
