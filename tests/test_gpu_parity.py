@@ -186,6 +186,39 @@ def test_abi_errors(fwr):
     assert e.value.status == F.FWR_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("n,N", [(40, 80), (128, 256)])
+def test_calls_are_ordered_on_the_plans_stream(fwr, n, N):
+    """A plan bound to a side stream reads its input after earlier work on that stream and
+    before later work on it; the result equals the null-stream result bit for bit."""
+    F = fwr
+    _flush(f"[gpu] side stream n={n} N={N}")
+    mask = I.pupil_mask(n)
+    cfg = SPHERE if n == 40 else ELT
+    slopes = (I.make_batch(I.SPHERE_40, 4, start=90, dtype=np.float32) if n == 40
+              else I.make_batch(I.ELT_128, 2, start=7, dtype=np.float32))
+    p = O.Params(n_iter=5, periodic=True, **cfg)
+    want = run_case(F, slopes, mask, p)
+    B = slopes.shape[0]
+    src = torch.from_numpy(slopes).cuda()
+    x = torch.zeros_like(src)
+    y = torch.full((B, n + 1, n + 1), -1.0, device="cuda")
+    big = torch.ones(1 << 26, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    plan = F.Plan(n, N, mask, n_iter=5, periodic=True, gamma=p.gamma, noise_var=p.noise_var, r0=p.r0,
+                  L0=p.L0, d=p.d, max_batch=B, stream=s.cuda_stream)
+    with torch.cuda.stream(s):
+        for _ in range(16):           # keeps the stream busy before the input is written
+            big.mul_(1.0)
+        x.copy_(src)
+        plan.reconstruct(x, y)
+        x.zero_()                     # overwriting the input afterwards must not reach the result
+        got = y.clone()
+    s.synchronize()
+    plan.close()
+    assert np.array_equal(got.cpu().numpy().astype(np.float64), want)
+
+
 def test_full_batch_sampled(fwr):
     """4096 frames in one launch (the batched workload); 12 frames checked against the oracle."""
     mask = I.pupil_mask(40)
