@@ -287,13 +287,15 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
 // ---------------------------------------------------------------- column phase
 // rows outside [rlo, rhi] (and, with `border`, other than 0 and N-1) are read as zeros;
 // only rows in [wlo, whi] are written back
-__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, int rlo, int rhi, int wlo, int whi,
-                                                      int border) {
+// (reads the spectrum from `in`, writes it to a.spec; the two may be the same field)
+__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float2 *in, const float *h, int rlo, int rhi,
+                                                      int wlo, int whi, int border) {
   __shared__ float2 L[R * LP];
   __shared__ float2 tw[NN];
   const int t = threadIdx.x, cl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, c0 = blockIdx.x * R;
   load_tw(tw, a.tw256, t);
+  const float2 *Sin = in + field(pair);
   float2 *S = a.spec + field(pair);
   // rows outside [rlo, rhi] load row rlo (a cache hit) and are replaced by zeros: every
   // load is issued first and kept unconditional, so that they are not serialised behind
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float *h, 
   for (int c_ = 0; c_ < NL; ++c_) {
     const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
     const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
-    v[c_] = S[(size_t)(in ? row : rlo) * NN + c0 + cc];
+    v[c_] = Sin[(size_t)(in ? row : rlo) * NN + c0 + cc];
   }
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
@@ -365,6 +367,78 @@ __global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
     const int i = t + c_ * THREADS;
     const int row = i / NN, p = i % NN;
     Ph[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+  }
+}
+
+// ---------------------------------------------------------------- inverse rows + next forward rows
+// One loop step between two column passes when phi is needed only by the next stencil: a
+// window block takes the spectrum rows m0-1 .. m0+16, runs their inverse row FFTs (phi rows,
+// kept in LDS), then the stencil (as row_fwd mode 1) and the forward row FFTs of its 16 rows.
+// The blocks' halo rows overlap, so the result goes to `out`, not back to a.spec.
+constexpr int FT = (R + 2) * 16;  // 18 lines of 16 threads
+__global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, int b0) {
+  __shared__ float2 L[(R + 2) * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
+  const bool own = rl < R;  // the threads of lines 16 and 17 transform but own no output row
+  const int m = m0 + (own ? rl : 0);
+  if (t < NN) load_tw(tw, a.tw256, t);
+  const float2 *S = a.spec + field(pair);
+#pragma unroll
+  for (int c_ = 0; c_ < (R + 2) * NN / FT; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * FT;
+    const int row = i / NN, p = i % NN;
+    L[row * LP + pad(p)] = S[(size_t)((m0 - 1 + row) & (NN - 1)) * NN + p];
+  }
+  const bool win_row = own && m >= a.o && m <= a.o + a.n;
+  const float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
+  float2 f0v[R];
+  uint32_t cv[R];
+  {
+    const size_t fr = (size_t)(win_row ? m - a.o : 0) * NN;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      f0v[q] = F0[fr + r + R * q];
+      cv[q] = a.codes[m * NN + r + R * q];
+    }
+  }
+  __syncthreads();
+  fft_stage_b<+1>(L + rl * LP, r);
+  __syncthreads();
+  fft_stage_a<+1>(L + rl * LP, r, tw);
+  __syncthreads();
+  // line j now holds phi row m0 - 1 + j; the stencil of row m reads lines rl .. rl + 2
+  const int sl = own ? rl : 0;
+  float2 fq[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int nn = r + R * q;
+    float2 f = f0v[q];
+    const uint32_t c = cv[q];
+    const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
+    const float2 p0 = L[(sl + 1) * LP + pad(nn)];
+    const float2 d1 = L[(sl + 2) * LP + pad(np)], d2 = L[sl * LP + pad(nm)];
+    const float2 d3 = L[(sl + 2) * LP + pad(nm)], d4 = L[sl * LP + pad(np)];
+    if (c & 1) f = cadd(f, csub(p0, d1));
+    if (c & 2) f = cadd(f, csub(p0, d2));
+    if (c & 4) f = cadd(f, csub(p0, d3));
+    if (c & 8) f = cadd(f, csub(p0, d4));
+    if (!win_row) f = make_float2(0.f, 0.f);  // (q2 = 0 on the other rows)
+    fq[q] = f;
+  }
+  __syncthreads();  // every stencil read of the phi rows is done
+#pragma unroll
+  for (int q = 0; q < R; ++q) L[rl * LP + pad(r + R * q)] = fq[q];
+  __syncthreads();
+  fft_stage_a<-1>(L + rl * LP, r, tw);  // (lines 16 and 17 are transformed too and dropped)
+  __syncthreads();
+  fft_stage_b<-1>(L + rl * LP, r);
+  __syncthreads();
+  if (t < NN) {
+    float2 *D = out + field(pair);
+#pragma unroll
+    for (int row = 0; row < R; ++row) D[(size_t)(m0 + row) * NN + t] = L[row * LP + pad(t)];
   }
 }
 
@@ -534,24 +608,31 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   };
   // start: q2 = F0 (also fills the F0 rows), forward row FFTs of the window rows
   hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 0, wb0, 0);
+  // Between two solves of the pruned loop phi only feeds the next stencil: the inverse and
+  // the next forward row pass run as one kernel, writing the spectrum to the s_y field (unused
+  // until after the loop), which the next column pass reads back into the spectrum field.
+  float2 *const spec2 = a.sy;
+  const float2 *col_in = a.spec;
   for (int it = 0; it < a.n_iter; ++it) {
     const bool last = it == a.n_iter - 1;
     // q2 is window-supported here unless per-iteration Eq. 5 made it explicit
     const bool win_in = !each || it == 0;
     const bool full_out = each || (last && explicit_final && !eq5_sums);  // phi needed on every row
-    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
+    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, col_in, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
                        full_out ? 0 : rlo, full_out ? NN - 1 : rhi, 0);
+    col_in = a.spec;
+    if (!last && !each) {
+      hipLaunchKernelGGL(row_inv_fwd_kernel, wrows, dim3(FT), 0, s, a, spec2, wb0);
+      col_in = spec2;
+      continue;
+    }
     if (full_out)
       hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
     else
       hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0);
     if (last) break;
-    if (each) {
-      explicit_q(false, true);
-      hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
-    } else {
-      hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0, 0);
-    }
+    explicit_q(false, true);  // per-iteration Eq. 5
+    hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
   }
   bool win_final = true;  // q2 of the final solve window-supported (plus rows 0 and N-1 with Eq. 5)
   bool border = false;
@@ -572,7 +653,7 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0, 0);
   }
   // the output is the window rows
-  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
+  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.spec, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
                      whi, border ? 1 : 0);
   hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0);
   hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);
