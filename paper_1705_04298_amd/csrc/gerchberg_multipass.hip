@@ -4,11 +4,13 @@
 // Same formulation as the on-chip kernel (two frames per complex field; the
 // loop step is q = G^T s, phi = TF^-1[TF(q) / |G|^2], s' = G phi; see
 // gerchberg_onchip.hip), split into grid-wide phases that exchange whole
-// fields through HBM (the 32 MiB working set of 64 frame pairs stays in the
-// MALL):
-//   row_fwd  : stencil (or F0 at the start) on 16-row blocks + forward row FFTs  -> SPEC
-//   col      : forward column FFTs, filter, inverse column FFTs on 16-column tiles (in place)
-//   row_inv  : inverse row FFTs -> PHI
+// fields through HBM (the 64 MiB working set of 64 frame pairs, two complex
+// fields each, stays in the MALL):
+//   row_fwd     : stencil (or F0 at the start) on 16-row blocks + forward row FFTs  -> SPEC
+//   col         : forward column FFTs, filter, inverse column FFTs on 16-column tiles
+//   row_inv     : inverse row FFTs -> PHI
+//   row_inv_fwd : between two solves of the pruned loop, row_inv and the next row_fwd in
+//                 one pass (phi stays in LDS)  -> second spectrum field, read by col
 // and, once per call, the explicit final step (cell slopes, Eq. 5 sums and
 // fix, scatter to q) and the output kernels.
 //
