@@ -257,6 +257,23 @@ fwr_status fwr_cnn_adam_step(fwr_cnn_t cnn, float lr);
 fwr_status fwr_cnn_set_stream(fwr_cnn_t cnn, void *stream);
 fwr_status fwr_cnn_destroy(fwr_cnn_t cnn);
 
+/* Learned start with the plain loop as fallback, in one call: the network's
+ * prediction (written to d_start, float[B][2][N][N]) starts Algorithm 1 with
+ * `plan` (its n_iter >= 1; phase to d_phase, float[B][n+1][n+1]; in-pupil
+ * residual of the last iteration to d_resid, float[B], as fwr_reconstruct_start);
+ * the frames whose residual exceeds `threshold` are then recomputed from the
+ * zero-padded start with `fallback` (same n and N, its own n_iter and Eq. 5
+ * setting) and their phase replaced.  *h_count (may be NULL) receives the
+ * number of recomputed frames.  plan, fallback and cnn must enqueue on the same
+ * stream and hold B frames (FWR_E_INVAL otherwise; on-chip grids only).  The
+ * call waits for the stream once, to size the fallback batch, so it cannot be
+ * captured in a graph.  The first call allocates gather buffers for
+ * fallback->max_batch frames in the fallback plan (freed by fwr_destroy); calls
+ * that share a fallback plan must not overlap. */
+fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn, const float *d_slopes,
+                                   float *d_start, float *d_phase, float *d_resid, float threshold, int32_t B,
+                                   int32_t *h_count);
+
 /* Static description of a status code (never NULL). */
 const char *fwr_status_string(int32_t status);
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwr.so")
 SOURCES = ["gerchberg_onchip.hip", "gerchberg_multipass.hip", "gerchberg_fourier.hip", "gen_screens.hip", "ext_hudgin.hip",
-           "cnn.hip", "fwr_api.cpp", "cnn_api.cpp"]
+           "cnn.hip", "fallback.hip", "fwr_api.cpp", "cnn_api.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 VALU instructions are disabled for all device code.

@@ -10,6 +10,7 @@
 
 #include "../../include/fwr.h"
 #include "cnn.h"
+#include "learned.h"
 
 using namespace fwr::cnn_launch;
 
@@ -50,6 +51,19 @@ struct fwr_cnn_s {
 namespace {
 
 bool valid(fwr_cnn_t c) { return c != nullptr && c->magic == kCnnMagic; }
+
+}  // namespace
+
+bool fwr::cnn_info(fwr_cnn_t c, int *n_sub, int *n_grid, int *max_batch, hipStream_t *stream) {
+  if (!valid(c)) return false;
+  *n_sub = c->n;
+  *n_grid = c->N;
+  *max_batch = c->max_batch;
+  *stream = c->stream;
+  return true;
+}
+
+namespace {
 
 fwr_status repack(fwr_cnn_t c) {
   for (int l = 0; l < kLayers; ++l) {

@@ -18,6 +18,7 @@
 #include "fourier.h"
 #include "gen.h"
 #include "hudgin.h"
+#include "learned.h"
 #include "multipass.h"
 #include "onchip.h"
 
@@ -56,6 +57,10 @@ struct fwr_plan_s {
   const uint8_t *dmask = nullptr;  // [n][n] valid subapertures on the device (generator)
   const int32_t *hudgin_src = nullptr;  // [2][N][N] source cells of the Hudgin extension (on-chip plans)
   double d = 0.0;                  // lenslet pitch [m]
+  // gather buffers when the plan serves as the fallback of fwr_reconstruct_learned (first use)
+  void *fb_mem = nullptr;
+  int32_t *fb_idx = nullptr, *fb_count = nullptr;
+  float *fb_slopes = nullptr, *fb_phase = nullptr;
 };
 
 namespace {
@@ -452,6 +457,60 @@ fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ex
   return fwr::hudgin_launch(a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
+fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn, const float *d_slopes,
+                                   float *d_start, float *d_phase, float *d_resid, float threshold, int32_t B,
+                                   int32_t *h_count) {
+  if (!valid(plan) || !valid(fallback)) return FWR_E_STATE;
+  int cn = 0, cN = 0, cmax = 0;
+  hipStream_t cs = nullptr;
+  if (!fwr::cnn_info(cnn, &cn, &cN, &cmax, &cs)) return FWR_E_STATE;
+  if (cn != plan->n || cN != plan->N || fallback->n != plan->n || fallback->N != plan->N) return FWR_E_INVAL;
+  if (cs != plan->stream || fallback->stream != plan->stream) return FWR_E_INVAL;
+  if (B < 0 || B > plan->max_batch || B > fallback->max_batch || B > cmax) return FWR_E_INVAL;
+  if (h_count != nullptr) *h_count = 0;
+  if (B == 0) return FWR_OK;
+  if (d_slopes == nullptr || d_start == nullptr || d_phase == nullptr || d_resid == nullptr ||
+      std::isnan(threshold))
+    return FWR_E_INVAL;
+  if (plan->multipass || plan->fourier) return FWR_E_UNSUPPORTED;
+  if (plan->n_iter < 1) return FWR_E_INVAL;  // the residual is that of the last iteration
+  const int n = plan->n;
+  const size_t per_s = (size_t)2 * n * n, per_p = (size_t)(n + 1) * (n + 1);
+  if (fallback->fb_mem == nullptr) {
+    const size_t mb = (size_t)fallback->max_batch;
+    const size_t idx_bytes = ((mb + 1) * sizeof(int32_t) + 255) / 256 * 256;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, idx_bytes + mb * (per_s + per_p) * sizeof(float)) != hipSuccess) return FWR_E_NOMEM;
+    fallback->fb_mem = mem;
+    fallback->fb_idx = static_cast<int32_t *>(mem);
+    fallback->fb_count = fallback->fb_idx + mb;
+    fallback->fb_slopes = reinterpret_cast<float *>(static_cast<char *>(mem) + idx_bytes);
+    fallback->fb_phase = fallback->fb_slopes + mb * per_s;
+  }
+  const hipStream_t st = plan->stream;
+  fwr_status r = fwr_cnn_forward(cnn, d_slopes, d_start, B);
+  if (r != FWR_OK) return r;
+  r = run(plan, d_slopes, d_phase, B, false, d_start, d_resid);
+  if (r != FWR_OK) return r;
+  if (fwr::fallback_select(d_resid, threshold, B, fallback->fb_idx, fallback->fb_count, st) != hipSuccess)
+    return FWR_E_DEVICE;
+  int32_t count = 0;
+  if (hipMemcpyAsync(&count, fallback->fb_count, sizeof(count), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return FWR_E_DEVICE;
+  if (count < 0 || count > B) return FWR_E_DEVICE;
+  if (count > 0) {
+    if (fwr::fallback_gather(d_slopes, fallback->fb_idx, fallback->fb_slopes, count, int(per_s), st) != hipSuccess)
+      return FWR_E_DEVICE;
+    r = run(fallback, fallback->fb_slopes, fallback->fb_phase, count, false);
+    if (r != FWR_OK) return r;
+    if (fwr::fallback_scatter(fallback->fb_phase, fallback->fb_idx, d_phase, count, int(per_p), st) != hipSuccess)
+      return FWR_E_DEVICE;
+  }
+  if (h_count != nullptr) *h_count = count;
+  return FWR_OK;
+}
+
 fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
   if (!valid(plan)) return FWR_E_STATE;
   plan->stream = static_cast<hipStream_t>(stream);
@@ -554,6 +613,7 @@ fwr_status fwr_destroy(fwr_plan_t plan) {
   if (!valid(plan)) return FWR_E_STATE;
   (void)hipStreamSynchronize(plan->stream);
   (void)hipFree(plan->d_mem);
+  (void)hipFree(plan->fb_mem);
   plan->magic = 0;
   delete plan;
   return FWR_OK;

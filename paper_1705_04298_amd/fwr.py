@@ -34,7 +34,7 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
-            "fwr_plan_autotune", "fwr_hudgin_extend")
+            "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned")
 CNN_PARAMS = 47714
 
 
@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_set_stream.restype = ctypes.c_int
     lib.fwr_cnn_destroy.argtypes = [vp]
     lib.fwr_cnn_destroy.restype = ctypes.c_int
+    lib.fwr_reconstruct_learned.argtypes = [vp, vp, vp, vp, vp, vp, vp, f32, i32, ctypes.POINTER(i32)]
+    lib.fwr_reconstruct_learned.restype = ctypes.c_int
     lib.fwr_hudgin_extend.argtypes = [vp, vp, vp, i32]
     lib.fwr_hudgin_extend.restype = ctypes.c_int
     lib.fwr_plan_set_group.argtypes = [vp, i32]
@@ -137,6 +139,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_generate.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def fwr_reconstruct_learned(plan, fallback, cnn, d_slopes: int, d_start: int, d_phase: int, d_resid: int,
+                            threshold: float, B: int, count=None) -> int:
+    return load().fwr_reconstruct_learned(plan, fallback, cnn, ctypes.c_void_p(d_slopes), ctypes.c_void_p(d_start),
+                                          ctypes.c_void_p(d_phase), ctypes.c_void_p(d_resid), float(threshold),
+                                          B, count)
 
 
 def status_string(status: int) -> str:

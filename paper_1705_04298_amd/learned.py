@@ -112,9 +112,11 @@ def train(frames: int, epochs: int, batch: int = 256, lr: float = 1e-3, seed: in
 
 
 class LearnedReconstructor:
-    """CNN start + `n_iter` Gerchberg iterations, with the plain-loop fallback.
+    """CNN start + `n_iter` Gerchberg iterations, with the plain-loop fallback
+    (`fwr_reconstruct_learned`: one library call).
 
-    `reconstruct(slopes)` returns (phase [B, n+1, n+1], residual [B], fallback mask [B]).
+    `reconstruct(slopes)` returns (phase [B, n+1, n+1], residual [B], number of frames recomputed
+    by the plain loop).
     """
 
     def __init__(self, params: np.ndarray, n_iter: int = 2, plain_iter: int = 10, threshold: float = 0.2,
@@ -125,20 +127,26 @@ class LearnedReconstructor:
         self.plan = fwr.Plan(N_SUB, N_GRID, mask, n_iter=n_iter, periodic=periodic, max_batch=max_batch)
         self.plain = fwr.Plan(N_SUB, N_GRID, mask, n_iter=plain_iter, periodic=periodic, max_batch=max_batch)
         self.threshold = float(threshold)
+        self._start = None
 
     def reconstruct(self, slopes, out=None):
+        import ctypes
         import torch
         B = slopes.shape[0]
-        start = self.net.forward(slopes)
+        self.plan._check(slopes, (B, 2, N_SUB, N_SUB), "slopes")
+        if out is None:
+            out = torch.empty((B, N_SUB + 1, N_SUB + 1), device=slopes.device, dtype=torch.float32)
+        self.plan._check(out, (B, N_SUB + 1, N_SUB + 1), "out")
+        if self._start is None or self._start.shape[0] < B:
+            self._start = torch.empty((B, 2, N_GRID, N_GRID), device=slopes.device, dtype=torch.float32)
         resid = torch.empty(B, device=slopes.device, dtype=torch.float32)
-        out = self.plan.reconstruct(slopes, out, start=start, resid=resid)
-        bad = resid > self.threshold
-        nbad = int(bad.sum().item())
-        if nbad:
-            idx = torch.nonzero(bad).flatten()
-            redo = self.plain.reconstruct(slopes.index_select(0, idx).contiguous())
-            out.index_copy_(0, idx, redo)
-        return out, resid, bad
+        count = ctypes.c_int32()
+        st = fwr.fwr_reconstruct_learned(self.plan.handle, self.plain.handle, self.net._h, slopes.data_ptr(),
+                                         self._start.data_ptr(), out.data_ptr(), resid.data_ptr(), self.threshold,
+                                         B, ctypes.byref(count))
+        if st != fwr.FWR_OK:
+            raise fwr.FwrError(st, "fwr_reconstruct_learned")
+        return out, resid, int(count.value)
 
     def close(self):
         self.net.close()
@@ -205,8 +213,8 @@ def evaluate(params: np.ndarray, frames: int = 4096, seed: int = 99, log=print, 
                                               if res[f"cnn_{k}"]["median_residual"] <= target), None)
     # fallback rate of the default learned reconstructor (CNN + 2 iterations, threshold 2x plain-10 level)
     lr = LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=2.0 * target, max_batch=frames)
-    _, resid, bad = lr.reconstruct(x)
-    res["fallback"] = {"threshold": 2.0 * target, "rate": float(bad.float().mean().item())}
+    _, resid, nfall = lr.reconstruct(x)
+    res["fallback"] = {"threshold": 2.0 * target, "rate": nfall / frames}
     lr.close()
     net.close()
     return res

@@ -38,4 +38,5 @@ def test_host_side_validation_without_gpu():
     h = ctypes.c_void_p()
     assert lib.fwr_plan(None, ctypes.byref(h)) == F.FWR_E_INVAL
     assert lib.fwr_destroy(None) == F.FWR_E_STATE
+    assert F.fwr_reconstruct_learned(None, None, None, 0, 0, 0, 0, 0.0, 1) == F.FWR_E_STATE
     assert sorted(F.EXPORTED) == sorted(declared_functions())

@@ -176,13 +176,80 @@ def test_trained_network_gains_over_zero_start(F):
     assert out[("cnn", 10)][1] < out[("plain", 10)][1], out
     # fallback: threshold 0 recomputes every frame with the plain loop (bit-identical to it)
     lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=0.0, max_batch=512)
-    ph, resid, bad = lr.reconstruct(x)
+    ph, resid, nfall = lr.reconstruct(x)
     plain = F.Plan(40, 80, mask, n_iter=10, periodic=True, max_batch=512)
-    assert bool(bad.all()) and torch.equal(ph, plain.reconstruct(x))
+    assert nfall == 512 and torch.equal(ph, plain.reconstruct(x))
     lr.close()
     lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=1e9, max_batch=512)
-    ph, resid, bad = lr.reconstruct(x)
-    assert not bool(bad.any())
+    ph, resid, nfall = lr.reconstruct(x)
+    assert nfall == 0
     lr.close()
     plain.close()
     net.close()
+
+
+@pytest.mark.parametrize("B,quantile", [(512, 0.5), (37, 0.9), (1, 0.0)])
+def test_learned_call_equals_its_steps(F, B, quantile):
+    """fwr_reconstruct_learned = network start, Algorithm 1 with the residual, then the plain loop
+    on exactly the frames above the threshold (in place): compared bit for bit with the same
+    steps called one by one, the frame selection done on the host."""
+    import os
+    from paper_1705_04298_amd import learned as L
+    _flush(f"[gpu] learned call B={B} q={quantile}")
+    params = np.load(os.path.join(os.path.dirname(L.__file__), "weights", "cnn_40x40_fried.npz"))["params"]
+    slopes, _ = L.make_frames(B, seed0=78_000)
+    x = torch.from_numpy(slopes).cuda()
+    mask = I.pupil_mask(40)
+    net = F.CNN(40, 80, mask, max_batch=B, input_scale=L.INPUT_SCALE)
+    net.set_params(params)
+    plan = F.Plan(40, 80, mask, n_iter=2, periodic=True, max_batch=B)
+    plain = F.Plan(40, 80, mask, n_iter=10, periodic=True, max_batch=B)
+    start = net.forward(x)
+    resid = torch.empty(B, device="cuda")
+    want = plan.reconstruct(x, start=start, resid=resid)
+    r = resid.cpu().numpy()
+    thr = float(np.quantile(r, quantile)) if quantile > 0 else -1.0
+    redo = np.flatnonzero(r > np.float32(thr))
+    if redo.size:
+        idx = torch.from_numpy(redo).cuda()
+        want[idx] = plain.reconstruct(x[idx].contiguous())
+    torch.cuda.synchronize()
+    lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=thr, max_batch=B)
+    got, got_resid, nfall = lr.reconstruct(x)
+    torch.cuda.synchronize()
+    assert nfall == redo.size
+    assert torch.equal(got_resid, resid)
+    assert torch.equal(got, want)
+    # a second call on the same objects (the fallback's gather buffers are reused)
+    got2, _, nfall2 = lr.reconstruct(x)
+    assert nfall2 == nfall and torch.equal(got2, want)
+    lr.close()
+    for h in (net, plan, plain):
+        h.close()
+
+
+def test_learned_call_rejects_mismatched_objects(F):
+    from paper_1705_04298_amd import learned as L
+    import ctypes
+    mask = I.pupil_mask(40)
+    net = F.CNN(40, 80, mask, max_batch=4, input_scale=L.INPUT_SCALE)
+    plan = F.Plan(40, 80, mask, n_iter=2, periodic=True, max_batch=4)
+    small = F.Plan(40, 80, mask, n_iter=10, periodic=True, max_batch=2)
+    other = F.Plan(24, 48, I.pupil_mask(24), n_iter=10, periodic=True, max_batch=4)
+    zero = F.Plan(40, 80, mask, n_iter=0, periodic=False, max_batch=4)
+    x = torch.zeros((4, 2, 40, 40), device="cuda")
+    st = torch.empty((4, 2, 80, 80), device="cuda")
+    ph = torch.empty((4, 41, 41), device="cuda")
+    r = torch.empty(4, device="cuda")
+    args = (x.data_ptr(), st.data_ptr(), ph.data_ptr(), r.data_ptr(), 0.1)
+    assert F.fwr_reconstruct_learned(plan.handle, small.handle, net._h, *args, 4) == F.FWR_E_INVAL   # B > fallback
+    assert F.fwr_reconstruct_learned(plan.handle, other.handle, net._h, *args, 4) == F.FWR_E_INVAL   # other grid
+    assert F.fwr_reconstruct_learned(zero.handle, plan.handle, net._h, *args, 4) == F.FWR_E_INVAL    # no iteration
+    assert F.fwr_reconstruct_learned(plan.handle, plan.handle, None, *args, 4) == F.FWR_E_STATE
+    assert F.fwr_reconstruct_learned(plan.handle, plan.handle, net._h, 0, *args[1:], 4) == F.FWR_E_INVAL
+    assert F.fwr_reconstruct_learned(plan.handle, plan.handle, net._h, *args[:4], float("nan"), 4) == F.FWR_E_INVAL
+    n = ctypes.c_int32(-1)
+    assert F.fwr_reconstruct_learned(plan.handle, plan.handle, net._h, *args, 0, ctypes.byref(n)) == F.FWR_OK
+    assert n.value == 0
+    for h in (net, plan, small, other, zero):
+        h.close()
