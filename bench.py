@@ -198,6 +198,7 @@ def main():
     if not args.no_autotune:
         plan.autotune(args.batch)  # launch shape (frames per workgroup) by timing
     threads, fpg, lds = plan.launch_info()
+    sched = plan.schedule
     out = torch.empty((args.batch, N_SUB + 1, N_SUB + 1), device="cuda", dtype=torch.float32)
     for _ in range(args.warmup):
         plan.reconstruct(x, out)
@@ -246,7 +247,8 @@ def main():
                                "10 Gerchberg iterations + Eq.5 + MMSE, von Karman D=8m r0=0.15m L0=25m, "
                                "noise 0.05 rad",
                    "batch": args.batch, "n_sub": N_SUB, "n_grid": N_GRID, "n_iter": N_ITER,
-                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds},
+                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds,
+                   "fft_radix_schedule": sched},
         "rms_phase_error_vs_oracle": parity,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": profiled_traffic(),
@@ -329,6 +331,7 @@ def sinc_main(args):
     if not args.no_autotune:
         plan.autotune(args.batch)
     threads, fpg, lds = plan.launch_info()
+    sched = plan.schedule
     out = torch.empty((args.batch, N_SUB + 1, N_SUB + 1), device="cuda")
     for _ in range(args.warmup):
         plan.reconstruct(x, out)
@@ -350,7 +353,8 @@ def sinc_main(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "4096 frames 40x40 SH, lenslet-averaging (sinc) slopes of von Karman screens, "
                                "padded 80x80, 10 iterations + Eq.5 + MMSE", "model": "sinc",
-                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds},
+                   "threads_per_group": threads, "frames_per_group": fpg, "lds_bytes_per_group": lds,
+                   "fft_radix_schedule": sched},
         "rms_phase_error_vs_oracle": {"frames": len(errs), "max_rel_rms": float(np.max(errs)),
                                       "median_rel_rms": float(np.median(errs)), "tolerance": 1e-5},
         "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,

@@ -130,10 +130,24 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream);
  * balances the waves of a workgroup over the four SIMDs of a CU. */
 fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
 
+/* Radix schedule of the on-chip kernel's in-lane DFTs (length T = N/4): 0 = radix
+ * 4 first, prime-factor (no twiddles) where the two factors are coprime (the
+ * default); 1 = Cooley-Tukey with twiddles at every level, radix 5 (else 3, else 2)
+ * first.  Both compute the exact DFT and round differently (each within the
+ * parity tolerance).  Schedule 1 exists for the windowed kernel of 2x-padded plans
+ * (n = N/2, N >= 24, no per-iteration Eq. 5; FWR_E_UNSUPPORTED otherwise,
+ * FWR_E_INVAL for other values); their calls with start values or the
+ * extended-slope output take schedule 0.  Plans start from the schedule
+ * autotuned earlier in the process for the same shape, else 0. */
+fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule);
+fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule);
+
 /* Autotuner: times every frames-per-workgroup choice of the plan on B frames (B <=
- * max_batch; device scratch is allocated and freed here) on the plan's stream,
- * synchronously, keeps the fastest in the plan and for later plans of the same shape,
- * and returns it in *frames_per_group (may be NULL).  Not for use under graph capture. */
+ * max_batch; device scratch is allocated and freed here), with each radix schedule
+ * the plan allows, on the plan's stream, synchronously; keeps the fastest pair in the
+ * plan and for later plans of the same shape, and returns the frames per workgroup
+ * in *frames_per_group (may be NULL; the schedule: fwr_plan_get_schedule).  Not for
+ * use under graph capture. */
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group);
 
 /* Launch shape of the reconstruction kernel, for reporting: threads per

@@ -176,9 +176,20 @@ constexpr int first_radix() {
   else return 5;
 }
 
+// radix taken first by the alternative schedule: the largest of 5, 3, 2 that divides L
+template <int L>
+constexpr int last_radix() {
+  if constexpr (L % 5 == 0) return 5;
+  else if constexpr (L % 3 == 0) return 3;
+  else return 2;
+}
+
 // Natural-order in-place DFT of length L on x[0..L-1]:
 //   X[k] = sum_n x[n] exp(DIR * 2 pi i n k / L), no scaling.
-template <int L, int DIR>
+// Radix schedule SCHED 0: radix 4 (else 2, 3, 5) first, prime-factor (Good-Thomas, no
+// twiddles) when the two factors are coprime; SCHED 1: Cooley-Tukey with twiddles at every
+// level, radix 5 (else 3, else 2) first.  Both are exact DFTs; they round differently.
+template <int L, int DIR, int SCHED = 0>
 __device__ __forceinline__ void dft(float2 *x) {
   if constexpr (L == 1) {
   } else if constexpr (L == 2) {
@@ -189,7 +200,7 @@ __device__ __forceinline__ void dft(float2 *x) {
     bfly4<DIR>(x);
   } else if constexpr (L == 5) {
     bfly5<DIR>(x);
-  } else if constexpr (std::gcd(first_radix<L>(), L / first_radix<L>()) == 1) {
+  } else if constexpr (SCHED == 0 && std::gcd(first_radix<L>(), L / first_radix<L>()) == 1) {
     // coprime factors L = R M: prime-factor (Good-Thomas) algorithm, no twiddles.
     // Input n = (M n1 + R n2) mod L, output k = (M M' k1 + R R' k2) mod L with
     // M M' = 1 (mod R), R R' = 1 (mod M); then W_L^(n k) = W_R^(n1 k1) W_M^(n2 k2).
@@ -211,12 +222,12 @@ __device__ __forceinline__ void dft(float2 *x) {
     });
   } else {
     static_assert(L % 2 == 0 || L % 3 == 0 || L % 5 == 0, "radix 2/3/5 lengths only");
-    constexpr int R = first_radix<L>();
+    constexpr int R = SCHED == 0 ? first_radix<L>() : last_radix<L>();
     constexpr int M = L / R;
     float2 s[R][M];
     static_for<0, R>([&](auto r) {
       static_for<0, M>([&](auto i) { s[r][i] = x[R * i + r]; });
-      dft<M, DIR>(s[r]);
+      dft<M, DIR, SCHED>(s[r]);
     });
     static_for<1, R>([&](auto r) {
       static_for<1, M>([&](auto k) { s[r][k] = twiddle<L, DIR, decltype(r)::value * decltype(k)::value>(s[r][k]); });
@@ -224,7 +235,7 @@ __device__ __forceinline__ void dft(float2 *x) {
     static_for<0, M>([&](auto k) {
       float2 t[R];
       static_for<0, R>([&](auto r) { t[r] = s[r][k]; });
-      dft<R, DIR>(t);
+      dft<R, DIR, SCHED>(t);
       static_for<0, R>([&](auto q) { x[k + M * q] = t[q]; });
     });
   }
@@ -324,22 +335,22 @@ __device__ __forceinline__ void line_fft_inv(float2 *x, const float2 *tw, int j,
 // Signed line transforms (see quad_dft_fwd_s): the forward one returns lane j's values
 // times S_j; the inverse one takes unsigned input and `twi[4 k + j]` = S_j conj(tw[4 k + j])
 // (with `sj` = S_j for k = 0), so that its output is unsigned.
-template <int T>
+template <int T, int SCHED = 0>
 __device__ __forceinline__ void line_fft_fwd_s(float2 *x, const float2 *tw, int j, const QuadLane &q) {
-  dft<T, -1>(x);
+  dft<T, -1, SCHED>(x);
 #pragma unroll
   for (int k = 1; k < T; ++k) x[k] = cmul(x[k], tw[4 * k + j]);
 #pragma unroll
   for (int k = 0; k < T; ++k) x[k] = quad_dft_fwd_s(x[k], q);
 }
-template <int T>
+template <int T, int SCHED = 0>
 __device__ __forceinline__ void line_fft_inv_s(float2 *x, const float2 *twi, int j, float sj, const QuadLane &q) {
 #pragma unroll
   for (int k = 0; k < T; ++k) x[k] = quad_dft_inv_s(x[k], q);
   x[0] = make_float2(sj * x[0].x, sj * x[0].y);
 #pragma unroll
   for (int k = 1; k < T; ++k) x[k] = cmul(x[k], twi[4 * k + j]);
-  dft<T, +1>(x);
+  dft<T, +1, SCHED>(x);
 }
 
 }  // namespace fwr

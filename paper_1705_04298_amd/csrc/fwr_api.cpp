@@ -47,6 +47,7 @@ struct fwr_plan_s {
   const float2 *tw_lane = nullptr;
   const uint32_t *codes = nullptr;
   int pairs = 1;  // frame pairs per workgroup of the on-chip kernel
+  int sched = 0;  // radix schedule of its in-lane DFTs (windowed kernel of 2x-padded plans)
   // Fourier-domain path (slope models without a compact stencil)
   bool fourier = false;
   fwr::FourierArgs fa{};
@@ -82,9 +83,11 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tuned;
 
-void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs, int model = FWR_MODEL_FRIED) {
+// stored value: launch unit (frame pairs, or frames for the Fourier-domain kernel) + 16 x schedule
+void remember_pairs(int device, int N, int n, int n_iter, bool each, int pairs, int model = FWR_MODEL_FRIED,
+                    int sched = 0) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tuned[TuneKey{device, N, n, n_iter, each, model}] = pairs;
+  g_tuned[TuneKey{device, N, n, n_iter, each, model}] = pairs + 16 * sched;
 }
 
 int tuned_value(int device, int N, int n, int n_iter, bool each, int model) {
@@ -99,7 +102,7 @@ int tuned_value(int device, int N, int n, int n_iter, bool each, int model) {
 // 3, 3, 2, 2); one pair elsewhere, where larger groups measured slower (they lower the
 // register budget per wave).
 int tuned_pairs(int device, int N, int n, int n_iter, bool each) {
-  if (const int v = tuned_value(device, N, n, n_iter, each, FWR_MODEL_FRIED)) return v;
+  if (const int v = tuned_value(device, N, n, n_iter, each, FWR_MODEL_FRIED)) return v % 16;
   const int waves = (fwr::onchip_threads(N, 1) + 63) / 64;
   if (waves > 4 && waves % 4 == 1 && fwr::onchip_pairs_ok(N, n, 2, each)) return 2;
   return 1;
@@ -239,6 +242,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
     return FWR_E_DEVICE;
   }
   plan->pairs = tuned_pairs(plan->device, N, n, p.n_iter, each);
+  plan->sched = tuned_value(plan->device, N, n, p.n_iter, each, FWR_MODEL_FRIED) / 16;
   const size_t b_h = h_loop.size() * sizeof(float);
   const size_t b_tw = tw.size() * sizeof(float2);
   const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
@@ -348,7 +352,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
   a.start = start;
   a.resid = resid;
-  return fwr::onchip_launch(plan->N, a, st, plan->pairs) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  return fwr::onchip_launch(plan->N, a, st, plan->pairs, plan->sched) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
 fwr_status fwr_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
@@ -554,6 +558,23 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
   return FWR_OK;
 }
 
+fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (schedule != 0 && schedule != 1) return FWR_E_INVAL;
+  if (schedule == 1 && (plan->multipass || plan->fourier || (plan->flags & fwr::kFlagPeriodicEach) != 0 ||
+                        !fwr::onchip_sched_ok(plan->N, plan->n)))
+    return FWR_E_UNSUPPORTED;
+  plan->sched = schedule;
+  return FWR_OK;
+}
+
+fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (schedule == nullptr) return FWR_E_INVAL;
+  *schedule = plan->sched;
+  return FWR_OK;
+}
+
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 1 || B > plan->max_batch) return FWR_E_INVAL;
@@ -580,22 +601,28 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
             hipMemsetAsync(d_in, 0, in_bytes, plan->stream) == hipSuccess;
-  const int before = *unit;
-  int best = before;
+  const int before = *unit, sched_before = plan->sched;
+  // radix schedules: both where the windowed on-chip kernel has two, else the first
+  const int n_sched = !plan->fourier && !each && fwr::onchip_sched_ok(N, n) ? 2 : 1;
+  int best = before, best_sched = sched_before;
   float best_ms = 0.f;
   for (int pairs : kPairsOptions) {
-    if (!ok) break;
-    if (!shape_ok(pairs)) continue;
-    *unit = pairs;
-    float ms = 0.f;
-    ok = run(plan, d_in, d_out, B, false) == FWR_OK && hipEventRecord(e0, plan->stream) == hipSuccess;
-    for (int r = 0; r < 3 && ok; ++r) ok = run(plan, d_in, d_out, B, false) == FWR_OK;
-    ok = ok && hipEventRecord(e1, plan->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    // a larger group must win by more than timing noise
-    if (ok && (best_ms == 0.f || ms < 0.97f * best_ms)) {
-      best = pairs;
-      best_ms = ms;
+    for (int sc = 0; sc < n_sched; ++sc) {
+      if (!ok) break;
+      if (!shape_ok(pairs)) continue;
+      *unit = pairs;
+      plan->sched = sc;
+      float ms = 0.f;
+      ok = run(plan, d_in, d_out, B, false) == FWR_OK && hipEventRecord(e0, plan->stream) == hipSuccess;
+      for (int r = 0; r < 3 && ok; ++r) ok = run(plan, d_in, d_out, B, false) == FWR_OK;
+      ok = ok && hipEventRecord(e1, plan->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      // a later candidate (larger group, second schedule) must win by more than timing noise
+      if (ok && (best_ms == 0.f || ms < 0.97f * best_ms)) {
+        best = pairs;
+        best_sched = sc;
+        best_ms = ms;
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -603,8 +630,10 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   (void)hipFree(d_in);
   (void)hipFree(d_out);
   *unit = ok ? best : before;
+  plan->sched = ok ? best_sched : sched_before;
   if (!ok) return FWR_E_DEVICE;
-  remember_pairs(plan->device, N, n, plan->n_iter, each, best, plan->fourier ? FWR_MODEL_SINC : FWR_MODEL_FRIED);
+  remember_pairs(plan->device, N, n, plan->n_iter, each, best, plan->fourier ? FWR_MODEL_SINC : FWR_MODEL_FRIED,
+                 plan->sched);
   if (frames_per_group) *frames_per_group = plan->fourier ? best : 2 * best;
   return FWR_OK;
 }

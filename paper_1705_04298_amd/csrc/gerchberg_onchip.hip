@@ -112,7 +112,9 @@ __device__ __forceinline__ float select_bits(bool c, float a, float b) {
 // WIN: the pruned loop of the 2x-padded window (n = N/2, o = N/4) with the window fixed at
 // compile time, so that the zero lines and columns outside it fold away (launched only
 // for such plans without start values or the extended-slope output).
-template <int N, bool EACH, int PAIRS, bool WIN = false>
+// SCHED: radix schedule of the in-lane DFTs (see dft in fft_lane.h); schedule 1 is built for
+// the WIN kernel of the sizes where the two schedules differ.
+template <int N, bool EACH, int PAIRS, bool WIN = false, int SCHED = 0>
 __global__ __launch_bounds__((Group<N, PAIRS>::THREADS))
 __attribute__((amdgpu_waves_per_eu(Group<N, PAIRS>::WAVES_PER_SIMD)))
 void gerchberg_onchip_kernel(OnchipArgs a) {
@@ -328,7 +330,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   // The signed transforms leave lane signs on the spectra: the row pass's on the LDS
   // columns it writes, the column pass's on its own values; the filter tables carry both.
   auto solve = [&](float2 *x, const float *h, bool fwd, bool inv, int mode) {
-    if (fwd) line_fft_fwd_s<T>(x, tw, j, q);
+    if (fwd) line_fft_fwd_s<T, SCHED>(x, tw, j, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];
     __syncthreads();
@@ -338,7 +340,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       const bool zero = (mode == 1 && !kin_w(k)) || (mode == 2 && !kin_w(k) && k != 0 && k != T - 1);
       y[k] = zero ? make_float2(0.f, 0.f) : buf[(4 * k + j) * P + col];
     }
-    line_fft_fwd_s<T>(y, tw, j, q);
+    line_fft_fwd_s<T, SCHED>(y, tw, j, q);
     const float *ht = h + t * T;  // thread-contiguous: one address, immediate offsets
 #pragma unroll
     for (int k = 0; k < T; ++k) {
@@ -346,7 +348,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       y[k].x *= hv;
       y[k].y *= hv;
     }
-    line_fft_inv_s<T>(y, twi, j, sj, q);
+    line_fft_inv_s<T, SCHED>(y, twi, j, sj, q);
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       if (mode == 1 ? kin_r(k) : kin_w(k)) buf[(4 * k + j) * P + col] = y[k];
@@ -355,7 +357,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     if (inv) {
 #pragma unroll
       for (int k = 0; k < T; ++k) x[k] = buf[line * P + T * j + k];
-      line_fft_inv_s<T>(x, twi, j, sj, q);
+      line_fft_inv_s<T, SCHED>(x, twi, j, sj, q);
     }
   };
 
@@ -702,8 +704,14 @@ constexpr bool win_instantiated() {
   return true;
 }
 
+// the second radix schedule differs from the first for in-lane lengths above 5
+template <int N>
+constexpr bool sched_instantiated() {
+  return Onchip<N>::T > 5;
+}
+
 template <int N, int PAIRS>
-hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
+hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s, int sched) {
   if constexpr (!pairs_instantiated<N, PAIRS>()) {
     return hipErrorInvalidValue;
   } else {
@@ -719,6 +727,12 @@ hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
       const bool win = a.n == N / 2 && a.o == N / 4 && a.start == nullptr && (a.flags & kFlagExtend) == 0;
       if constexpr (win_instantiated<PAIRS>()) {
         if (win) {
+          if constexpr (sched_instantiated<N>()) {
+            if (sched == 1) {
+              hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false, PAIRS, true, 1>), grid, block, dyn, s, a);
+              return hipGetLastError();
+            }
+          }
           hipLaunchKernelGGL((gerchberg_onchip_kernel<N, false, PAIRS, true>), grid, block, dyn, s, a);
           return hipGetLastError();
         }
@@ -730,12 +744,12 @@ hipError_t launch_pairs(const OnchipArgs &a, hipStream_t s) {
 }
 
 template <int N>
-hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s, int pairs) {
+hipError_t launch_onchip(const OnchipArgs &a, hipStream_t s, int pairs, int sched) {
   switch (pairs) {
-    case 1: return launch_pairs<N, 1>(a, s);
-    case 2: return launch_pairs<N, 2>(a, s);
-    case 4: return launch_pairs<N, 4>(a, s);
-    case 8: return launch_pairs<N, 8>(a, s);
+    case 1: return launch_pairs<N, 1>(a, s, sched);
+    case 2: return launch_pairs<N, 2>(a, s, sched);
+    case 4: return launch_pairs<N, 4>(a, s, sched);
+    case 8: return launch_pairs<N, 8>(a, s, sched);
     default: return hipErrorInvalidValue;
   }
 }
@@ -747,14 +761,16 @@ hipError_t prepare_pairs(int n) {
   } else {
     // dynamic LDS above the default 64 KiB window must be requested explicitly
     const int dyn = Onchip<N>::F0_IN_LDS ? PAIRS * (n + 1) * Onchip<N>::PITCH * 8 : 0;
-    const void *fns[3] = {reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS>),
+    const void *fns[4] = {reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS>),
                           PAIRS == 1 ? reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, true, 1>)
                                      : nullptr,
-                          nullptr};
+                          nullptr, nullptr};
     if constexpr (win_instantiated<PAIRS>())
       fns[2] = reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS, true>);
+    if constexpr (sched_instantiated<N>())
+      fns[3] = reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS, true, 1>);
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
       if (fns[i]) e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     return e;
   }
@@ -839,9 +855,19 @@ hipError_t onchip_prepare(int N, int n, int pairs) {
   }
 }
 
-hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs) {
+bool onchip_sched_ok(int N, int n) {
+  if (2 * n != N || N % 4 != 0) return false;
   switch (N) {
-#define FWR_CASE(NN) case NN: return launch_onchip<NN>(a, s, pairs);
+#define FWR_CASE(NN) case NN: return sched_instantiated<NN>();
+    FWR_ONCHIP_SIZES(FWR_CASE)
+#undef FWR_CASE
+    default: return false;
+  }
+}
+
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs, int sched) {
+  switch (N) {
+#define FWR_CASE(NN) case NN: return launch_onchip<NN>(a, s, pairs, sched);
     FWR_ONCHIP_SIZES(FWR_CASE)
 #undef FWR_CASE
     default: return hipErrorInvalidValue;

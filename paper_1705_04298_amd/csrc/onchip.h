@@ -30,6 +30,9 @@ bool onchip_pairs_ok(int N, int n, int pairs, bool periodic_each);  // instantia
 int onchip_threads(int N, int pairs);                  // per workgroup
 int onchip_lds_bytes(int N, int n, int pairs);         // per workgroup, static + dynamic
 hipError_t onchip_prepare(int N, int n, int pairs);    // before the first launch with `pairs`
-hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs);
+// `sched`: radix schedule of the in-lane DFTs (0 or 1) for the windowed kernel of 2x-padded
+// plans (onchip_sched_ok); other launches take schedule 0
+bool onchip_sched_ok(int N, int n);
+hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs, int sched);
 
 }  // namespace fwr

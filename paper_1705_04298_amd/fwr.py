@@ -34,7 +34,8 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_cnn_create", "fwr_cnn_set_params", "fwr_cnn_get_params", "fwr_cnn_forward",
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
-            "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned")
+            "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned", "fwr_plan_set_schedule",
+            "fwr_plan_get_schedule")
 CNN_PARAMS = 47714
 
 
@@ -130,6 +131,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_hudgin_extend.restype = ctypes.c_int
     lib.fwr_plan_set_group.argtypes = [vp, i32]
     lib.fwr_plan_set_group.restype = ctypes.c_int
+    lib.fwr_plan_set_schedule.argtypes = [vp, i32]
+    lib.fwr_plan_set_schedule.restype = ctypes.c_int
+    lib.fwr_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.fwr_plan_get_schedule.restype = ctypes.c_int
     lib.fwr_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.fwr_plan_autotune.restype = ctypes.c_int
     lib.fwr_reconstruct_group.argtypes = [ctypes.POINTER(FwrWork), i32, vp]
@@ -350,8 +355,23 @@ class Plan:
         if st != FWR_OK:
             raise FwrError(st, "fwr_plan_set_group")
 
+    def set_schedule(self, schedule: int):
+        """Radix schedule of the in-lane DFTs (0 or 1; fwr_plan_set_schedule)."""
+        st = load().fwr_plan_set_schedule(self._h, int(schedule))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_plan_set_schedule")
+
+    @property
+    def schedule(self) -> int:
+        v = ctypes.c_int32()
+        st = load().fwr_plan_get_schedule(self._h, ctypes.byref(v))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_plan_get_schedule")
+        return int(v.value)
+
     def autotune(self, B: Optional[int] = None) -> int:
-        """Time every launch shape on B frames, keep the fastest; returns frames per workgroup."""
+        """Time every launch shape and radix schedule on B frames, keep the fastest; returns frames per
+        workgroup (the schedule: `schedule`)."""
         out = ctypes.c_int32()
         st = load().fwr_plan_autotune(self._h, int(B or self.max_batch), ctypes.byref(out))
         if st != FWR_OK:

@@ -93,10 +93,72 @@ def test_autotune_picks_a_valid_group(F):
     plan.set_group(2)
     want = plan.reconstruct(x)
     fpg = plan.autotune(512)
-    assert fpg in (2, 4) and plan.launch_info()[1] == fpg
-    assert torch.equal(plan.reconstruct(x), want)
+    assert fpg in (2, 4) and plan.launch_info()[1] == fpg and plan.schedule in (0, 1)
+    got = plan.reconstruct(x)
+    if plan.schedule == 0:
+        assert torch.equal(got, want)
+    else:  # the other radix schedule rounds differently
+        assert float(((got - want) ** 2).mean() / (want ** 2).mean()) ** 0.5 <= 2e-5
     # a later plan of the same shape starts from the tuned choice
     other = F.Plan(40, 80, mask, n_iter=10, periodic=True, max_batch=64)
-    assert other.launch_info()[1] == fpg
+    assert other.launch_info()[1] == fpg and other.schedule == plan.schedule
     other.close()
+    plan.close()
+
+
+SCHED_GRIDS = [(24, 12), (32, 16), (40, 20), (48, 24), (64, 32), (80, 40), (128, 64)]
+
+
+def _rel(got, want):
+    return np.sqrt(np.mean((got - want) ** 2) / np.mean(want ** 2))
+
+
+@pytest.mark.parametrize("N,n", SCHED_GRIDS)
+def test_second_radix_schedule_matches_oracle(F, N, n):
+    """Radix schedule 1 (Cooley-Tukey, radix 5/3/2 first) against the oracle, and the same bits for
+    every frames-per-workgroup choice under it."""
+    _flush(f"[gpu] radix schedule 1 N={N} n={n}")
+    mask = I.pupil_mask(n)
+    d = 8.0 / n
+    plan = F.Plan(n, N, mask, n_iter=10, periodic=True, max_batch=5, d=d)
+    plan.set_schedule(0)
+    x, _ = plan.generate(5, 1234)
+    p0 = plan.reconstruct(x).clone()
+    plan.set_schedule(1)
+    assert plan.schedule == 1
+    p1 = plan.reconstruct(x).clone()
+    torch.cuda.synchronize()
+    s64 = x.cpu().numpy().astype(np.float64)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=10, periodic=True, d=d)
+    for b in range(5):
+        want = O.reconstruct(s64[b], mask, p)
+        assert _rel(p0[b].cpu().numpy().astype(np.float64), want) <= 1e-5, (0, b)
+        assert _rel(p1[b].cpu().numpy().astype(np.float64), want) <= 1e-5, (1, b)
+    for fpg in (2, 4, 8, 16):
+        try:
+            plan.set_group(fpg)
+        except F.FwrError:
+            continue
+        assert torch.equal(plan.reconstruct(x), p1), fpg
+    plan.close()
+
+
+def test_schedule_choices_outside_the_windowed_kernel(F):
+    _flush("[gpu] radix schedule errors")
+    cases = [F.Plan(40, 80, I.pupil_mask(40), max_batch=2, model="sinc"),      # Fourier-domain kernel
+             F.Plan(78, 80, I.pupil_mask(78), max_batch=2),                    # not 2x padded
+             F.Plan(10, 20, I.pupil_mask(10), max_batch=2),                    # T = 5: one schedule
+             F.Plan(40, 80, I.pupil_mask(40), max_batch=2, periodic_each_iter=True),
+             F.Plan(128, 256, I.pupil_mask(128), max_batch=2)]                 # multi-pass
+    for plan in cases:
+        plan.set_schedule(0)
+        with pytest.raises(F.FwrError) as e:
+            plan.set_schedule(1)
+        assert e.value.status == F.FWR_E_UNSUPPORTED
+        assert plan.schedule == 0
+        plan.close()
+    plan = F.Plan(40, 80, I.pupil_mask(40), max_batch=2)
+    with pytest.raises(F.FwrError) as e:
+        plan.set_schedule(2)
+    assert e.value.status == F.FWR_E_INVAL
     plan.close()
