@@ -392,14 +392,31 @@ def uneven_main(args):
                                                 "cnn_40x40_fried.npz"))["params"])
             starts[-1] = torch.empty((B, 2, 2 * n, 2 * n), device="cuda")
     work = [(p, x, o, s, None) for p, x, o, s in zip(plans, xs, outs, starts)]
+    # with the network, its frames (network, then their loop) form a branch of their own on a
+    # second stream, beside the grouped loops of the other sizes
+    learned = [w for w in work if w[3] is not None]
+    others = [w for w in work if w[3] is None]
+    branch = torch.cuda.Stream()
 
     def step():
         for p, x, c in zip(plans, xs, ctrs):
             p.generate(x.shape[0], seed, counter=c, slopes=x, r0=0.15, L0=25.0, sigma=0.05)
-        for x, s in zip(xs, starts):
-            if s is not None:
+        if net is None:
+            fwr.reconstruct_group(work)
+            return
+        main = torch.cuda.current_stream()
+        branch.wait_stream(main)
+        with torch.cuda.stream(branch):
+            net.set_stream()
+            for p, x, o, s, _ in learned:
+                p.set_stream()
                 net.forward(x, s)
-        fwr.reconstruct_group(work)
+                p.reconstruct(x, o, start=s)
+        net.set_stream()
+        for p, _, _, _, _ in learned:
+            p.set_stream()
+        fwr.reconstruct_group(others)
+        main.wait_stream(branch)
 
     def rebind():
         for p in plans:

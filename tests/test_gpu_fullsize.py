@@ -3,8 +3,9 @@ on the GPU, sampled frames against the FP64 oracle (needs an MI355X).
 
   * 128 frames of 128x128 subapertures padded to 256x256, 20 iterations (multi-pass path);
   * the mixed closed-loop step: 2048 x 24x24, 2048 x 40x40 (network start), 512 x 64x64 and
-    64 x 128x128 frames, padded 2x, 10 iterations, generated on the device and reconstructed by
-    one grouped call, captured in a HIP graph and replayed.
+    64 x 128x128 frames, padded 2x, 10 iterations, generated on the device; the network's frames
+    on a branch of their own beside one grouped call for the others; captured in a HIP graph and
+    replayed.
 """
 import os
 import sys
@@ -81,14 +82,26 @@ def test_mixed_step_graph_replays_sampled(F):
                                                 "cnn_40x40_fried.npz"))["params"])
             starts[-1] = torch.empty((B, 2, 2 * n, 2 * n), device="cuda")
     work = [(p, x, o, s, None) for p, x, o, s in zip(plans, xs, outs, starts)]
+    learned = [w for w in work if w[3] is not None]
+    others = [w for w in work if w[3] is None]
+    branch = torch.cuda.Stream()
 
-    def step():
+    def step():  # as bench.py times it: the network's frames on a branch beside the grouped loops
         for p, x, c in zip(plans, xs, ctrs):
             p.generate(x.shape[0], seed, counter=c, slopes=x, r0=0.15, L0=25.0, sigma=0.05)
-        for x, s in zip(xs, starts):
-            if s is not None:
+        main = torch.cuda.current_stream()
+        branch.wait_stream(main)
+        with torch.cuda.stream(branch):
+            net.set_stream()
+            for p, x, o, s, _ in learned:
+                p.set_stream()
                 net.forward(x, s)
-        F.reconstruct_group(work)
+                p.reconstruct(x, o, start=s)
+        net.set_stream()
+        for p, _, _, _, _ in learned:
+            p.set_stream()
+        F.reconstruct_group(others)
+        main.wait_stream(branch)
 
     def rebind():
         for p in plans:
