@@ -596,8 +596,10 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   const bool each = (a.flags & kMPPeriodicEach) != 0;
   const bool explicit_final = periodic || extend || (each && a.n_iter > 0);
   const bool fix_final = periodic || (each && a.n_iter > 0);
-  // Eq. 5 after the loop from the in-pupil misfits, without full slope fields
-  const bool eq5_sums = periodic && !extend && !each && a.n_iter > 0;
+  // Eq. 5 after the loop from the in-pupil misfits, without full slope fields.  Its border-row
+  // blocks write node rows 0 and N-1, which must not be window rows: with o = 1 row N-1 = o + n
+  // is one, so that case takes the explicit path.
+  const bool eq5_sums = periodic && !extend && !each && a.n_iter > 0 && a.o >= 2;
   // window rows [o, o+n] and the stencil's reach [o-1, o+n+1]; their row blocks
   // (with o = 1 the reach wraps around: every row)
   const int wlo = a.o, whi = a.o + a.n;

@@ -143,6 +143,21 @@ def test_second_radix_schedule_matches_oracle(F, N, n):
     plan.close()
 
 
+def test_grouped_call_keeps_each_plans_schedule(F):
+    _flush("[gpu] radix schedule in a grouped call")
+    items = []
+    for n, sched in ((20, 1), (40, 0), (64, 1)):
+        plan = F.Plan(n, 2 * n, I.pupil_mask(n), n_iter=4, periodic=True, max_batch=3, d=8.0 / n)
+        plan.set_schedule(sched)
+        x, _ = plan.generate(3, 77)
+        items.append((plan, x, torch.empty((3, n + 1, n + 1), device="cuda"), None, None))
+    F.reconstruct_group(items)
+    torch.cuda.synchronize()
+    for plan, x, o, _, _ in items:
+        assert torch.equal(o, plan.reconstruct(x)), plan.n_sub
+        plan.close()
+
+
 def test_schedule_choices_outside_the_windowed_kernel(F):
     _flush("[gpu] radix schedule errors")
     cases = [F.Plan(40, 80, I.pupil_mask(40), max_batch=2, model="sinc"),      # Fourier-domain kernel

@@ -97,15 +97,26 @@ def test_lsq_final_filter(fwr):
 
 @pytest.mark.parametrize("N,n", [(8, 4), (8, 6), (12, 6), (16, 8), (16, 2), (20, 10), (24, 12),
                                  (32, 16), (40, 20), (48, 24), (64, 32), (80, 78), (128, 64),
-                                 (256, 128), (256, 250)])
+                                 (256, 128), (256, 250), (256, 252), (256, 254)])
 def test_grid_sizes(fwr, N, n):
     """Every grid size (on-chip N <= 128, multi-pass N = 256), random masks, white slopes;
-    includes n = N - 2 (thin border)."""
+    includes n = N - 2 (thin border; at N = 256 the stencil's reach then wraps round the grid)."""
     mask = I.random_mask(n, seed=N * 1000 + n)
     slopes = I.random_slopes(3, n, seed=N + n)
     p = O.Params(n_sub=n, n_grid=N, n_iter=6, periodic=True, gamma=1.0, noise_var=0.01, r0=0.15,
                  L0=25.0, d=8.0 / n)
     check_reconstruct(fwr, slopes, mask, p, f"grid{N}")
+
+
+@pytest.mark.parametrize("periodic,each,n_iter", [(False, False, 5), (True, True, 3), (True, False, 1)])
+def test_thin_border_multipass(fwr, periodic, each, n_iter):
+    """N = 256 with a one-cell border (n = 254, o = 1): the stencil's reach wraps round the grid and
+    node row N-1 is a window row."""
+    mask = I.random_mask(254, seed=254)
+    slopes = I.random_slopes(2, 254, seed=7)
+    p = O.Params(n_sub=254, n_grid=256, n_iter=n_iter, periodic=periodic, periodic_each_iter=each, gamma=1.0,
+                 noise_var=0.01, r0=0.15, L0=25.0, d=39.0 / 254)
+    check_reconstruct(fwr, slopes, mask, p, "thin256")
 
 
 @pytest.mark.parametrize("periodic", [False, True])
