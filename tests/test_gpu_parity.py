@@ -277,3 +277,21 @@ def test_elt128_extend(fwr, periodic):
         assert np.abs(got[b, 0] - ref.sx).max() <= 10 * REL_TOL * scale
         assert np.abs(got[b, 1] - ref.sy).max() <= 10 * REL_TOL * scale
         assert np.array_equal(got[b, 0, o:o + 128, o:o + 128][m].astype(np.float32), slopes[b, 0][m])
+
+
+@pytest.mark.parametrize("n", [254, 252])
+def test_thin_border_multipass_extend(fwr, n):
+    mask = I.random_mask(n, seed=n + 1)
+    slopes = I.random_slopes(2, n, seed=n + 2).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=256, n_iter=4, periodic=True, gamma=1.0, noise_var=0.01, r0=0.15, L0=25.0,
+                 d=39.0 / n)
+    _flush(f"[gpu] thin-border extend n={n}")
+    got = run_case(fwr, slopes, mask, p, what="extend")
+    o = (256 - n) // 2
+    m = mask.astype(bool)
+    for b in range(2):
+        ref = O.extend(slopes[b].astype(np.float64), mask, p)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(got[b, 0] - ref.sx).max() <= 10 * REL_TOL * scale
+        assert np.abs(got[b, 1] - ref.sy).max() <= 10 * REL_TOL * scale
+        assert np.array_equal(got[b, 0, o:o + n, o:o + n][m].astype(np.float32), slopes[b, 0][m])
