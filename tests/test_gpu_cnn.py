@@ -133,6 +133,33 @@ def test_start_values_match_oracle(F, periodic):
     plan.close()
 
 
+@pytest.mark.parametrize("N,n", [(8, 6), (16, 2), (24, 12), (48, 24), (80, 78), (128, 64), (128, 126)])
+def test_start_values_on_every_grid(F, N, n):
+    """Start values, extended slopes and the residual on thin borders, odd windows and random masks."""
+    _flush(f"[gpu] start values N={N} n={n}")
+    mask = I.random_mask(n, seed=N + n)
+    slopes = I.random_slopes(2, n, seed=3 * N + n).astype(np.float32)
+    start = np.random.default_rng(N * n).standard_normal((2, 2, N, N)).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=3, periodic=True, noise_var=0.01, d=8.0 / n)
+    plan = F.Plan(n, N, mask, n_iter=3, periodic=True, noise_var=0.01, d=8.0 / n, max_batch=2)
+    x = torch.from_numpy(slopes).cuda()
+    st = torch.from_numpy(start).cuda()
+    resid = torch.empty(2, device="cuda")
+    ext = plan.extend(x, start=st, resid=resid).cpu().numpy().astype(np.float64)
+    phase = plan.reconstruct(x, start=st).cpu().numpy().astype(np.float64)
+    r = resid.cpu().numpy()
+    for b in range(2):
+        s64 = slopes[b].astype(np.float64)
+        st64 = (start[b, 0].astype(np.float64), start[b, 1].astype(np.float64))
+        ref = O.extend(s64, mask, p, start=st64)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(ext[b, 0] - ref.sx).max() <= 1e-4 * scale
+        assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
+        assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
+        assert rel(phase[b], O.reconstruct(s64, mask, p, start=st64)) <= 1e-5
+    plan.close()
+
+
 def test_residual_of_the_plain_loop(F):
     mask = I.pupil_mask(40)
     slopes = I.make_batch(I.SPHERE_40, 4, start=240, dtype=np.float32)

@@ -21,7 +21,7 @@ def F():
     return fwr
 
 
-@pytest.mark.parametrize("n,N", [(40, 80), (24, 48), (12, 24), (64, 128)])
+@pytest.mark.parametrize("n,N", [(40, 80), (24, 48), (12, 24), (64, 128), (78, 80)])
 def test_hudgin_extension_and_phase(F, n, N):
     print(f"[gpu] hudgin n={n} N={N}", flush=True)
     sys.stdout.flush()
