@@ -108,6 +108,17 @@ def test_grid_sizes(fwr, N, n):
     check_reconstruct(fwr, slopes, mask, p, f"grid{N}")
 
 
+@pytest.mark.parametrize("N,n", [(8, 6), (16, 2), (24, 12), (48, 24), (80, 78), (128, 64), (128, 126)])
+@pytest.mark.parametrize("periodic,each", [(False, False), (True, True)])
+def test_grid_sizes_other_eq5_modes(fwr, N, n, periodic, each):
+    """Without Eq. 5, and with Eq. 5 after every iteration, on thin borders and odd windows."""
+    mask = I.random_mask(n, seed=N * 1001 + n)
+    slopes = I.random_slopes(3, n, seed=N + 2 * n)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=4, periodic=periodic, periodic_each_iter=each, gamma=1.0,
+                 noise_var=0.01, r0=0.15, L0=25.0, d=8.0 / n)
+    check_reconstruct(fwr, slopes, mask, p, f"grid{N}")
+
+
 @pytest.mark.parametrize("periodic,each,n_iter", [(False, False, 5), (True, True, 3), (True, False, 1)])
 def test_thin_border_multipass(fwr, periodic, each, n_iter):
     """N = 256 with a one-cell border (n = 254, o = 1): the stencil's reach wraps round the grid and
