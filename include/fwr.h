@@ -86,7 +86,10 @@ typedef struct {
   double d;                 /* lenslet pitch [m] (grid spacing of the phase) */
   const double *alpha_map;  /* optional HOST N*N map (row = frequency l along y, column =
                                frequency k along x, unshifted DFT order) that replaces
-                               gamma * W_eta / W_phi; NULL = use gamma, noise_var, r0, L0, d */
+                               gamma * W_eta / W_phi; NULL = use gamma, noise_var, r0, L0, d.
+                               Finite, >= 0 and even, map[(N-l)%N][(N-k)%N] = map[l][k], as
+                               the ratio of two spectra of real processes is (FWR_E_INVAL
+                               otherwise); copied at plan time */
   int32_t max_batch;        /* largest B accepted by the calls, >= 1 */
   void *stream;             /* hipStream_t for every call; NULL = the null stream */
 } fwr_params;

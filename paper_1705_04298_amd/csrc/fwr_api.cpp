@@ -172,6 +172,17 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const int n = p.n_sub, N = p.n_grid;
   if (n < 1 || N <= n || (N - n) % 2 != 0 || p.mask == nullptr) return FWR_E_INVAL;
   if (p.n_iter < 0 || p.n_iter > 10000 || p.max_batch < 1) return FWR_E_INVAL;
+  if (N > 256) return FWR_E_UNSUPPORTED;
+  if (p.alpha_map != nullptr) {
+    // W_eta / W_phi of real processes: finite, >= 0 and even, alpha(-l, -k) = alpha(l, k); the
+    // kernels' Fourier operators must be real and even (two frames share a complex field)
+    for (int l = 0; l < N; ++l)
+      for (int k = 0; k < N; ++k) {
+        const double a = p.alpha_map[(size_t)l * N + k];
+        if (!(a >= 0.0) || !std::isfinite(a) || a != p.alpha_map[(size_t)((N - l) % N) * N + (N - k) % N])
+          return FWR_E_INVAL;
+      }
+  }
   if (p.model == FWR_MODEL_SINC) return plan_fourier(p, out);
   if (p.model != FWR_MODEL_FRIED) return FWR_E_UNSUPPORTED;
   if (p.alpha_map == nullptr && p.gamma != 0.0) {

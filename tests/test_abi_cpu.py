@@ -40,3 +40,25 @@ def test_host_side_validation_without_gpu():
     assert lib.fwr_destroy(None) == F.FWR_E_STATE
     assert F.fwr_reconstruct_learned(None, None, None, 0, 0, 0, 0, 0.0, 1) == F.FWR_E_STATE
     assert sorted(F.EXPORTED) == sorted(declared_functions())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfwr.so not built")
+def test_alpha_map_must_be_even_and_non_negative():
+    """The plan rejects a map of W_eta/W_phi that is not even (or negative) before any device work."""
+    import numpy as np
+    from paper_1705_04298_amd import fwr as F
+    lib = F.load()
+    n, N = 4, 8
+    mask = np.ones((n, n), dtype=np.uint8)
+    for bad in ("odd", "negative"):
+        alpha = np.ones((N, N))
+        if bad == "odd":
+            alpha[1, 2] = 2.0             # alpha[7, 6] stays 1
+        else:
+            alpha[0, 0] = -1.0
+        p = F.FwrParams()
+        p.n_sub, p.n_grid, p.n_iter, p.periodic, p.max_batch, p.gamma = n, N, 2, 1, 1, 1.0
+        p.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.alpha_map = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = ctypes.c_void_p()
+        assert lib.fwr_plan(ctypes.byref(p), ctypes.byref(h)) == F.FWR_E_INVAL, bad

@@ -306,3 +306,29 @@ def test_thin_border_multipass_extend(fwr, n):
         assert np.abs(got[b, 0] - ref.sx).max() <= 10 * REL_TOL * scale
         assert np.abs(got[b, 1] - ref.sy).max() <= 10 * REL_TOL * scale
         assert np.array_equal(got[b, 0, o:o + n, o:o + n][m].astype(np.float32), slopes[b, 0][m])
+
+
+@pytest.mark.parametrize("n,N,model", [(40, 80, "fried"), (20, 40, "fried"), (128, 256, "fried"), (40, 80, "sinc")])
+def test_alpha_map_replaces_the_regulariser(fwr, n, N, model):
+    """A caller's map of gamma W_eta / W_phi (row = frequency l along y, column = k along x; even,
+    not symmetric under l <-> k) in the final filter: against the oracle's extension and Eq. 2/3
+    with that map."""
+    _flush(f"[gpu] alpha map n={n} N={N} {model}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(3, n, seed=N + 5).astype(np.float32)
+    rng = np.random.default_rng(N)
+    raw = 0.05 + rng.uniform(0.0, 0.5, (N, N)) * (1.0 + np.arange(N)[None, :] / N)
+    neg = (-np.arange(N)) % N
+    alpha = 0.5 * (raw + raw[neg][:, neg])  # even, as a ratio of spectra of real processes is
+    assert not np.allclose(alpha, alpha.T)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=4, periodic=True, d=8.0 / n, model=model)
+    plan = fwr.Plan(n, N, mask, n_iter=4, periodic=True, d=p.d, alpha_map=alpha, max_batch=3, model=model)
+    got = plan.reconstruct(torch.from_numpy(slopes).cuda()).cpu().numpy().astype(np.float64)
+    plan.close()
+    Gx, Gy, S = O.slope_model(model, N)
+    Rx, Ry = O.wiener_reconstructor(Gx, Gy, 1.0, alpha, S)
+    o = (N - n) // 2
+    for b in range(3):
+        ext = O.extend(slopes[b].astype(np.float64), mask, p)
+        want = O.fourier_reconstruct(ext.sx, ext.sy, Rx, Ry)[o:o + n + 1, o:o + n + 1]
+        assert rel_rms(got[b], want) <= REL_TOL, b
