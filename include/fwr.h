@@ -221,7 +221,8 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
  * first_frame + i (+ *d_counter when d_counter != NULL) of the sequence keyed
  * by `seed` (Philox4x32-10 counters, so a frame does not depend on its batch);
  * first_frame must be even.  When d_counter (DEVICE uint64) is given it is
- * advanced by the batch size afterwards, so a graph replay draws fresh frames.
+ * advanced by the batch size rounded up to even afterwards (frames come in pairs), so a graph
+ * replay draws fresh frames.
  * d_slopes: float[B][2][n][n]; d_phase (optional): float[B][n+1][n+1] true node phase.
  * Random numbers, for frame pair p (frames 2p, 2p+1) and key (seed low, seed high word):
  *   spectral sample (l, k), l, k in [0, N): Philox counter (p low, p high, l N + k, 0),

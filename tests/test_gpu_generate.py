@@ -74,6 +74,13 @@ def test_generator_counter_and_batch_independence(F):
     assert torch.equal(part, whole[6:])
     with pytest.raises(F.FwrError):
         plan.generate(2, SEED, first_frame=3)  # odd first frame
+    # an odd batch moves the counter on to the next pair: frames 0-2, then 4-6
+    counter.zero_()
+    c, _ = plan.generate(3, SEED, counter=counter)
+    d, _ = plan.generate(3, SEED, counter=counter)
+    torch.cuda.synchronize()
+    assert int(counter.item()) == 8
+    assert torch.equal(c, whole[:3]) and torch.equal(d, whole[4:7])
     plan.close()
 
 
