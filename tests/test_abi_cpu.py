@@ -62,3 +62,21 @@ def test_alpha_map_must_be_even_and_non_negative():
         p.alpha_map = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         h = ctypes.c_void_p()
         assert lib.fwr_plan(ctypes.byref(p), ctypes.byref(h)) == F.FWR_E_INVAL, bad
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfwr.so not built")
+def test_cnn_create_validates_on_the_host():
+    import numpy as np
+    from paper_1705_04298_amd import fwr as F
+    lib = F.load()
+    mask = np.ones((6, 6), dtype=np.uint8)
+    mp = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    h = ctypes.c_void_p()
+    assert lib.fwr_cnn_create(6, 12, mp, 1, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_UNSUPPORTED  # N < 16
+    assert lib.fwr_cnn_create(6, 20, mp, 1, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_UNSUPPORTED  # N^2 % 64
+    assert lib.fwr_cnn_create(6, 16, None, 1, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_INVAL
+    assert lib.fwr_cnn_create(6, 16, mp, 0, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_INVAL
+    assert lib.fwr_cnn_create(6, 16, mp, 1, 0.0, 0, None, ctypes.byref(h)) == F.FWR_E_INVAL
+    assert lib.fwr_cnn_create(6, 15, mp, 1, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_INVAL       # N - n odd
+    assert lib.fwr_cnn_forward(None, None, None, 1) == F.FWR_E_STATE
+    assert lib.fwr_cnn_destroy(None) == F.FWR_E_STATE

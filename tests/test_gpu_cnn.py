@@ -280,3 +280,20 @@ def test_learned_call_rejects_mismatched_objects(F):
     assert n.value == 0
     for h in (net, plan, small, other, zero):
         h.close()
+
+
+def test_cnn_call_errors(F):
+    mask = I.pupil_mask(40)
+    net = F.CNN(40, 80, mask, max_batch=2, input_scale=SCALE, training=False)
+    x = torch.zeros((3, 2, 40, 40), device="cuda")
+    with pytest.raises(F.FwrError) as e:
+        net.forward(x)                                   # B > max_batch
+    assert e.value.status == F.FWR_E_INVAL
+    with pytest.raises(F.FwrError) as e:
+        net.set_params(np.zeros(10, dtype=np.float32))   # wrong parameter count
+    assert e.value.status == F.FWR_E_INVAL
+    pred = net.forward(x[:2])
+    with pytest.raises(F.FwrError) as e:
+        net.backward(pred, torch.zeros_like(pred))       # inference network: no gradients
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+    net.close()
