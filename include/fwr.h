@@ -266,7 +266,8 @@ fwr_status fwr_cnn_forward(fwr_cnn_t cnn, const float *d_slopes, float *d_pred, 
 /* After fwr_cnn_forward on the same batch (training mode): loss = mean over the
  * out-of-pupil cells of both channels of (scaled prediction - scaled target)^2,
  * gradients of every parameter into the plan's gradient buffer; *h_loss (may be
- * NULL) receives the loss (the call then waits for the stream). */
+ * NULL) receives the loss (the call then waits for the stream).  Clears its
+ * gradient buffers with memsets: not for graph capture. */
 fwr_status fwr_cnn_backward(fwr_cnn_t cnn, const float *d_pred, const float *d_target, int32_t B, float *h_loss);
 fwr_status fwr_cnn_get_grads(fwr_cnn_t cnn, float *h_grads, int32_t count);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
