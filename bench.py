@@ -381,6 +381,8 @@ def uneven_main(args):
     for n, B, d in UNEVEN:
         plan = fwr.Plan(n, 2 * n, I.pupil_mask(n), n_iter=N_ITER, periodic=True, gamma=1.0,
                         noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=d, max_batch=B)
+        if not args.no_autotune:
+            plan.autotune(B)  # frames per workgroup and radix schedule, by timing
         plans.append(plan)
         xs.append(torch.empty((B, 2, n, n), device="cuda"))
         outs.append(torch.empty((B, n + 1, n + 1), device="cuda"))
@@ -469,7 +471,8 @@ def uneven_main(args):
         "eager_ms_per_step": eager_ms,
         "config": {"workload": "2048x24^2 + 2048x40^2 (CNN start) + 512x64^2 + 64x128^2 SH frames, padded 2x, "
                                "10 iterations + Eq.5 + MMSE, fresh von Karman frames each step",
-                   "items": [{"n_sub": n, "frames": B} for n, B, _ in UNEVEN],
+                   "items": [{"n_sub": n, "frames": B, "frames_per_group": p.launch_info()[1],
+                              "fft_radix_schedule": p.schedule} for (n, B, _), p in zip(UNEVEN, plans)],
                    "learned_start": net is not None},
     }
     for p in plans:
