@@ -51,7 +51,7 @@ extern "C" {
 typedef enum {
   FWR_OK = 0,
   FWR_E_INVAL = -1,        /* bad argument (NULL pointer, size out of range, ...) */
-  FWR_E_UNSUPPORTED = -2,  /* valid request this build does not implement (e.g. grid size) */
+  FWR_E_UNSUPPORTED = -2,  /* valid request the library does not implement (e.g. grid size) */
   FWR_E_NOMEM = -3,        /* device allocation failed */
   FWR_E_DEVICE = -4,       /* HIP runtime error (launch failure, fault, no device) */
   FWR_E_STATE = -5         /* plan handle not valid */
