@@ -278,6 +278,10 @@ def test_learned_call_rejects_mismatched_objects(F):
     n = ctypes.c_int32(-1)
     assert F.fwr_reconstruct_learned(plan.handle, plan.handle, net._h, *args, 0, ctypes.byref(n)) == F.FWR_OK
     assert n.value == 0
+    side = torch.cuda.Stream()
+    net.set_stream(side.cuda_stream)                                                               # other stream
+    assert F.fwr_reconstruct_learned(plan.handle, plan.handle, net._h, *args, 4) == F.FWR_E_INVAL
+    net.set_stream()
     for h in (net, plan, small, other, zero):
         h.close()
 
