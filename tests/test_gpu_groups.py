@@ -158,6 +158,22 @@ def test_grouped_call_keeps_each_plans_schedule(F):
         plan.close()
 
 
+def test_grouped_call_mixes_slope_models_and_paths(F):
+    """A group of a lenslet-averaging (sinc) plan, a Fried on-chip plan and a multi-pass plan gives
+    the bits of the individual calls."""
+    _flush("[gpu] grouped call, mixed models")
+    items = []
+    for n, N, model in ((40, 80, "sinc"), (24, 48, "fried"), (128, 256, "fried")):
+        plan = F.Plan(n, N, I.pupil_mask(n), n_iter=3, periodic=True, max_batch=3, d=8.0 / n, model=model)
+        x = torch.from_numpy(I.random_slopes(3, n, seed=n).astype(np.float32)).cuda()
+        items.append((plan, x, torch.empty((3, n + 1, n + 1), device="cuda"), None, None))
+    F.reconstruct_group(items)
+    torch.cuda.synchronize()
+    for plan, x, o, _, _ in items:
+        assert torch.equal(o, plan.reconstruct(x)), (plan.n_sub, plan.model)
+        plan.close()
+
+
 def test_schedule_choices_outside_the_windowed_kernel(F):
     _flush("[gpu] radix schedule errors")
     cases = [F.Plan(40, 80, I.pupil_mask(40), max_batch=2, model="sinc"),      # Fourier-domain kernel
