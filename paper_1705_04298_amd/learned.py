@@ -214,7 +214,11 @@ def evaluate(params: np.ndarray, frames: int = 4096, seed: int = 99, log=print, 
     # fallback rate of the default learned reconstructor (CNN + 2 iterations, threshold 2x plain-10 level)
     lr = LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=2.0 * target, max_batch=frames)
     _, resid, nfall = lr.reconstruct(x)
-    res["fallback"] = {"threshold": 2.0 * target, "rate": nfall / frames}
+    ms_lr = timed(lambda: lr.reconstruct(x))  # network, 2 iterations, fallback (one host sync per call)
+    res["fallback"] = {"threshold": 2.0 * target, "rate": nfall / frames, "ms_per_batch": ms_lr,
+                       "frames_per_s": frames / ms_lr * 1e3}
+    log(f"[learned] cnn + 2 it + fallback (threshold {2.0 * target:.4f}): {100 * nfall / frames:.1f} % "
+        f"recomputed, {frames / ms_lr * 1e3:.0f} frames/s")
     lr.close()
     net.close()
     return res
