@@ -166,7 +166,8 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
  * outside the pupil instead; inside the pupil the measurement is used as
  * always.  `d_resid` (float[B], may be NULL) receives the in-pupil misfit of
  * the last iteration, ||P (G phi - s0)|| / ||P s0|| (0 when n_iter = 0 or the
- * pupil is empty).  On-chip grids only (N <= 128); FWR_E_UNSUPPORTED otherwise.
+ * pupil is empty).  On-chip grids (N <= 128) of both slope models; FWR_E_UNSUPPORTED
+ * for the multi-pass grid (N = 256).
  * With n_iter = 0 the start is the extension: fwr_reconstruct_start then applies
  * Eq. 2/3 to (measurement inside, start outside); it needs periodic = 0 and no
  * residual, and fwr_extend_start needs n_iter >= 1 (FWR_E_INVAL otherwise).

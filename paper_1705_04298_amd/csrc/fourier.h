@@ -13,6 +13,8 @@ enum : int { kFourierPeriodic = 1, kFourierExtend = 4 };
 struct FourierArgs {
   const float *slopes;     // [B][2][n][n]
   float *out;              // [B][n+1][n+1], or [B][2][N][N] with kFourierExtend
+  const float *start;      // optional [B][2][N][N]: start slopes outside the pupil (NULL = zeros)
+  float *resid;            // optional [B]: in-pupil misfit of the last iteration
   const float *alpha;      // [4N][T]: loop coefficient of Z (real), column-phase slot k of thread t
   const float2 *beta;      // [4N][T]: loop coefficient of conj(Z(-l, -k))
   const float2 *fin_a;     // [4N][T]: final coefficient of Z

@@ -328,19 +328,21 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (in == nullptr || out == nullptr) return FWR_E_INVAL;
-  if ((start != nullptr || resid != nullptr) && (plan->multipass || plan->fourier)) return FWR_E_UNSUPPORTED;
-  if (plan->fourier) {
-    fwr::FourierArgs a = plan->fa;
-    a.slopes = in;
-    a.out = out;
-    a.B = B;
-    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) | (extend ? fwr::kFourierExtend : 0);
-    return fwr::fourier_launch(plan->N, a, st, plan->frames) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
-  }
+  if ((start != nullptr || resid != nullptr) && plan->multipass) return FWR_E_UNSUPPORTED;
   // with no iteration the start is the extension itself: Eq. 2/3 of (measurement inside, start
   // outside); the extended-slope output, Eq. 5 and the residual need iterations
   if (start != nullptr && plan->n_iter == 0 && (extend || resid != nullptr || (plan->flags & fwr::kFlagPeriodic)))
     return FWR_E_INVAL;
+  if (plan->fourier) {
+    fwr::FourierArgs a = plan->fa;
+    a.slopes = in;
+    a.out = out;
+    a.start = start;
+    a.resid = resid;
+    a.B = B;
+    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) | (extend ? fwr::kFourierExtend : 0);
+    return fwr::fourier_launch(plan->N, a, st, plan->frames) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  }
   if (plan->multipass) {
     fwr::MPArgs a = plan->mp;
     a.slopes = in;

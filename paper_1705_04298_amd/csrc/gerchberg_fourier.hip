@@ -96,12 +96,14 @@ void fourier_kernel(FourierArgs a) {
   const bool in_rows = line >= o && line < o + n;
   const int mrow = (in_rows ? line - o : 0) * P + T * j;
 
-  float2 x[T];  // s_x + i s_y of cells (line, 4k + j)
+  float2 x[T];  // s_x + i s_y of cells (line, 4k + j): the measurement, zeros or the start outside
+  const float *stf = a.start ? a.start + (size_t)f * 2 * N * N + (size_t)line * N + j : nullptr;
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     const bool in = in_rows && ((pup >> k) & 1u);
     const float2 v = meas[mrow + k];
-    x[k] = make_float2(select_bits(in, v.x, 0.f), select_bits(in, v.y, 0.f));
+    const float ox = stf ? stf[4 * k] : 0.f, oy = stf ? stf[N * N + 4 * k] : 0.f;
+    x[k] = make_float2(select_bits(in, v.x, ox), select_bits(in, v.y, oy));
   }
 
   // column-phase frequencies: LDS column c holds x-frequency kf(c); slot k of lane j holds
@@ -154,8 +156,36 @@ void fourier_kernel(FourierArgs a) {
     line_fft_inv<T>(x, tw, j, q);
   };
 
+  if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) a.resid[f] = 0.f;
   for (int it = 0; it < a.n_iter; ++it) {
     solve(false);
+    if (a.resid != nullptr && it == a.n_iter - 1) {
+      // in-pupil misfit of the last iteration, before step 4: ||P (s' - s0)|| / ||P s0||
+      float num = 0.f, den = 0.f;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const bool in = in_rows && ((pup >> k) & 1u);
+        const float2 v = meas[mrow + k];
+        const float dx = x[k].x - v.x, dy = x[k].y - v.y;
+        num += in ? dx * dx + dy * dy : 0.f;
+        den += in ? v.x * v.x + v.y * v.y : 0.f;
+      }
+      num += dpp_xor1(num);
+      num += dpp_xor2(num);
+      den += dpp_xor1(den);
+      den += dpp_xor2(den);
+      if (j == 0) sums[line] = make_float2(num, den);
+      __syncthreads();
+      if (t == 0) {  // fixed-order sum over the lines
+        float nt = 0.f, dt = 0.f;
+        for (int m = 0; m < N; ++m) {
+          nt += sums[m].x;
+          dt += sums[m].y;
+        }
+        if (active) a.resid[f] = dt > 0.f ? sqrtf(nt / dt) : 0.f;
+      }
+      __syncthreads();  // the line sums are read before the buffer is used again
+    }
     // step 4: the measurement inside the pupil, the extrapolation outside
 #pragma unroll
     for (int k = 0; k < T; ++k) {

@@ -96,11 +96,48 @@ def test_sinc_unsupported_calls(F):
     plan = F.Plan(40, 80, mask, n_iter=2, max_batch=2, model="sinc")
     x = torch.zeros((2, 2, 40, 40), device="cuda")
     with pytest.raises(F.FwrError):
-        plan.reconstruct(x, start=torch.zeros((2, 2, 80, 80), device="cuda"))
-    with pytest.raises(F.FwrError):
         plan.generate(2, 1)
     with pytest.raises(F.FwrError):
         F.Plan(128, 256, I.pupil_mask(128), max_batch=1, model="sinc")
     with pytest.raises(F.FwrError):
         F.Plan(40, 80, mask, periodic_each_iter=True, max_batch=1, model="sinc")
     plan.close()
+
+
+@pytest.mark.parametrize("N,n,periodic", [(80, 40, True), (80, 40, False), (48, 24, True), (80, 78, True)])
+def test_sinc_start_values_and_residual(F, N, n, periodic):
+    """Start values outside the pupil and the last iteration's in-pupil residual under the sinc
+    model, against the oracle (phase, extended slopes, residual)."""
+    _flush(f"[gpu] sinc start N={N} n={n} periodic={periodic}")
+    mask = I.random_mask(n, seed=N + 3 * n)
+    slopes = I.random_slopes(3, n, seed=N * 7 + n).astype(np.float32)
+    start = np.random.default_rng(N + n).standard_normal((3, 2, N, N)).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=3, periodic=periodic, d=8.0 / n, model="sinc")
+    plan = _plan(F, p, mask, 3)
+    x = torch.from_numpy(slopes).cuda()
+    st = torch.from_numpy(start).cuda()
+    resid = torch.empty(3, device="cuda")
+    ext = plan.extend(x, start=st, resid=resid).cpu().numpy().astype(np.float64)
+    r = resid.cpu().numpy()
+    phase = plan.reconstruct(x, start=st).cpu().numpy().astype(np.float64)
+    for b in range(3):
+        s64 = slopes[b].astype(np.float64)
+        st64 = (start[b, 0].astype(np.float64), start[b, 1].astype(np.float64))
+        ref = O.extend(s64, mask, p, start=st64)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(ext[b, 0] - ref.sx).max() <= 1e-4 * scale
+        assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
+        assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
+        assert _rel(phase[b], O.reconstruct(s64, mask, p, start=st64)) <= 1e-5
+    # the residual without start values, and zero with no iteration
+    r0 = torch.empty(3, device="cuda")
+    plan.reconstruct(x, resid=r0)
+    ref0 = O.extend(slopes[0].astype(np.float64), mask, p)
+    assert abs(float(r0[0]) - ref0.residuals[-1]) <= 1e-4 * ref0.residuals[-1]
+    plan.close()
+    p0 = O.Params(n_sub=n, n_grid=N, n_iter=0, periodic=False, d=8.0 / n, model="sinc")
+    plan0 = _plan(F, p0, mask, 3)
+    rz = torch.full((3,), 7.0, device="cuda")
+    plan0.reconstruct(x, resid=rz)
+    assert bool((rz == 0).all())
+    plan0.close()
