@@ -185,9 +185,9 @@ fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const f
  * row from the edge of the pupil, then Eq. 5.  Every cell outside the pupil takes the
  * slope of the nearest in-pupil cell of its column (x) or row (y), the upper / left one
  * on a tie (this also fills the central obstruction); a line without in-pupil cells is
- * zero.  d_slopes: float[B][2][n][n]; d_ext: float[B][2][N][N].  On-chip Fried plans only
- * (FWR_E_UNSUPPORTED otherwise).  The phase of this extension is fwr_reconstruct_start on
- * a plan with n_iter = 0 and periodic = 0 with d_ext as the start.
+ * zero.  d_slopes: float[B][2][n][n]; d_ext: float[B][2][N][N].  On-chip plans of either
+ * slope model (FWR_E_UNSUPPORTED for N = 256).  The phase of this extension is
+ * fwr_reconstruct_start on a plan with n_iter = 0 and periodic = 0 with d_ext as the start.
  */
 fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B);
 

@@ -145,6 +145,37 @@ void filter_values(const fwr_params &p, int l, int k, double &hl, double &hf) {
   hf = den > 0.0 ? norm / den : 0.0;
 }
 
+// Hudgin extension (Sec. 3.2): the source cell of every grid cell, x slopes from the nearest
+// in-pupil cell of the column, y slopes from the nearest of the row (upper / left on a tie),
+// -1 where the line has none; [2][N][N]
+std::vector<int32_t> hudgin_sources(const fwr_params &p) {
+  const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
+  auto in_pupil = [&](int cm, int cn) {
+    const int i = cm - o, jj = cn - o;
+    return i >= 0 && i < n && jj >= 0 && jj < n && p.mask[(size_t)i * n + jj] != 0;
+  };
+  std::vector<int32_t> hsrc(2 * (size_t)N * N, -1);
+  for (int m = 0; m < N; ++m)
+    for (int c = 0; c < N; ++c) {
+      int best = -1, bd = N + 1;
+      for (int r = 0; r < N; ++r)
+        if (in_pupil(r, c) && std::abs(r - m) < bd) {
+          bd = std::abs(r - m);
+          best = (r - o) * n + (c - o);
+        }
+      hsrc[(size_t)m * N + c] = best;
+      best = -1;
+      bd = N + 1;
+      for (int q = 0; q < N; ++q)
+        if (in_pupil(m, q) && std::abs(q - c) < bd) {
+          bd = std::abs(q - c);
+          best = (m - o) * n + (q - o);
+        }
+      hsrc[(size_t)N * N + (size_t)m * N + c] = best;
+    }
+  return hsrc;
+}
+
 fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out);
 fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out);
 
@@ -258,26 +289,7 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   const size_t b_tw = tw.size() * sizeof(float2);
   const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = 2 * b_h + b_tw;
   const size_t off_dmask = off_codes + codes.size() * sizeof(uint32_t);
-  // Hudgin extension: the nearest in-pupil cell of the column (x) / row (y), upper / left on a tie
-  std::vector<int32_t> hsrc(2 * (size_t)N * N, -1);
-  for (int m = 0; m < N; ++m)
-    for (int c = 0; c < N; ++c) {
-      int best = -1, bd = N + 1;
-      for (int r = 0; r < N; ++r)
-        if (in_pupil(r, c) && std::abs(r - m) < bd) {
-          bd = std::abs(r - m);
-          best = (r - o) * n + (c - o);
-        }
-      hsrc[(size_t)m * N + c] = best;
-      best = -1;
-      bd = N + 1;
-      for (int q = 0; q < N; ++q)
-        if (in_pupil(m, q) && std::abs(q - c) < bd) {
-          bd = std::abs(q - c);
-          best = (m - o) * n + (q - o);
-        }
-      hsrc[(size_t)N * N + (size_t)m * N + c] = best;
-    }
+  const std::vector<int32_t> hsrc = hudgin_sources(p);
   const size_t off_hudgin = (off_dmask + (size_t)n * n + 15) & ~size_t(15);
   const size_t total = off_hudgin + hsrc.size() * sizeof(int32_t);
   std::vector<uint8_t> dmask((size_t)n * n);
@@ -842,8 +854,10 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   }
   const size_t b_a = alpha.size() * sizeof(float), b_c = betat.size() * sizeof(float2);
   const size_t b_tw = tw.size() * sizeof(float2), b_p = pup.size() * sizeof(uint32_t);
+  const std::vector<int32_t> hsrc = hudgin_sources(p);
+  const size_t b_h = hsrc.size() * sizeof(int32_t);
   const size_t off_b = b_a, off_fa = off_b + b_c, off_fb = off_fa + b_c, off_tw = off_fb + b_c,
-               off_p = off_tw + b_tw, total = off_p + b_p;
+               off_p = off_tw + b_tw, off_h = (off_p + b_p + 15) & ~size_t(15), total = off_h + b_h;
   char *mem = nullptr;
   if (hipMalloc(reinterpret_cast<void **>(&mem), total) != hipSuccess) {
     delete plan;
@@ -855,6 +869,8 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   if (e == hipSuccess) e = hipMemcpy(mem + off_fb, fin_b.data(), b_c, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(mem + off_p, pup.data(), b_p, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_h, hsrc.data(), b_h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = fwr::hudgin_prepare(N);
   if (e != hipSuccess) {
     (void)hipFree(mem);
     delete plan;
@@ -867,6 +883,7 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   a.fin_b = reinterpret_cast<const float2 *>(mem + off_fb);
   a.tw_lane = reinterpret_cast<const float2 *>(mem + off_tw);
   a.inpupil = reinterpret_cast<const uint32_t *>(mem + off_p);
+  plan->hudgin_src = reinterpret_cast<const int32_t *>(mem + off_h);
   a.n = n;
   a.o = o;
   a.n_iter = p.n_iter;

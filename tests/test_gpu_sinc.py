@@ -141,3 +141,24 @@ def test_sinc_start_values_and_residual(F, N, n, periodic):
     plan0.reconstruct(x, resid=rz)
     assert bool((rz == 0).all())
     plan0.close()
+
+
+@pytest.mark.parametrize("n,N", [(40, 80), (24, 48)])
+def test_sinc_hudgin_extension(F, n, N):
+    """The Hudgin extension on a lenslet-averaging plan, then Eq. 2/3 of the sinc model from it."""
+    _flush(f"[gpu] sinc hudgin n={n} N={N}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(3, n, seed=N + n + 11).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=0, periodic=False, d=8.0 / n, model="sinc")
+    plan0 = _plan(F, p, mask, 3)
+    x = torch.from_numpy(slopes).cuda()
+    ext = plan0.hudgin_extend(x)
+    phase = plan0.reconstruct(x, start=ext).cpu().numpy().astype(np.float64)
+    ext = ext.cpu().numpy().astype(np.float64)
+    for b in range(3):
+        s0x, s0y, P = O.padded_measurement(slopes[b].astype(np.float64), mask, N)
+        rx, ry = O.hudgin_extend(s0x, s0y, P)
+        assert np.array_equal(ext[b, 0, :, :N - 1], rx[:, :N - 1])
+        assert np.array_equal(ext[b, 1, :N - 1, :], ry[:N - 1, :])
+        assert _rel(phase[b], O.reconstruct_hudgin(slopes[b].astype(np.float64), mask, p)) <= 1e-5
+    plan0.close()
