@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwr.so")
-SOURCES = ["gerchberg_onchip.hip", "gerchberg_multipass.hip", "gerchberg_fourier.hip", "gen_screens.hip", "ext_hudgin.hip",
+# (source, extra define): the on-chip kernel file is compiled once per group of grid sizes
+SOURCES = [("gerchberg_onchip.hip", f"FWR_ONCHIP_UNIT={u}") for u in range(5)] + ["gerchberg_multipass.hip", "gerchberg_fourier.hip", "gen_screens.hip", "ext_hudgin.hip",
            "cnn.hip", "fallback.hip", "fwr_api.cpp", "cnn_api.cpp"]
 ARCH = "gfx950"
 
@@ -30,14 +31,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libfwr)")
 
 
-def build(verbose: bool = False, resource_usage: bool = False, defines=(), out: str = LIB) -> str:
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-function", *DEVICE_FLAGS, *[f"-D{d}" for d in defines]]
-    if resource_usage:
-        cmd += ["-Rpass-analysis=kernel-resource-usage"]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = out + ".tmp"
-    cmd += ["-o", tmp]
+def _compile(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,7 +43,34 @@ def build(verbose: bool = False, resource_usage: bool = False, defines=(), out: 
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{shown}")
     if verbose and shown.strip():
         print(shown)
-    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, resource_usage: bool = False, defines=(), out: str = LIB, jobs: int = 0) -> str:
+    """Compile every source to an object in parallel, then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    base = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC",
+            "-Wall", "-Wno-unused-function", *DEVICE_FLAGS, *[f"-D{d}" for d in defines]]
+    if resource_usage:
+        base += ["-Rpass-analysis=kernel-resource-usage"]
+    tag = f"{os.getpid()}_{abs(hash((out, tuple(defines)))) % 10**8}"
+    objdir = os.path.join(os.path.dirname(out), f"_build_{tag}")
+    os.makedirs(objdir, exist_ok=True)
+    units = [s if isinstance(s, tuple) else (s, None) for s in SOURCES]
+    objs = [os.path.join(objdir, f"{os.path.splitext(s)[0]}{'' if d is None else '_' + d.split('=')[1]}.o")
+            for s, d in units]
+    cmds = [base + ([] if d is None else [f"-D{d}"]) + ["-c", os.path.join(CSRC, s), "-o", o]
+            for (s, d), o in zip(units, objs)]
+    jobs = jobs or min(len(cmds), max(1, len(os.sched_getaffinity(0))), 16)
+    try:
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_compile, c, verbose) for c in cmds]:
+                f.result()
+        tmp = out + ".tmp"
+        _compile([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        os.replace(tmp, out)
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
     return out
 
 

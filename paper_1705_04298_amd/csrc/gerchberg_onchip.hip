@@ -810,6 +810,44 @@ bool pairs_ok(int n, int pairs, bool each) {
 
 #define FWR_ONCHIP_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(128)
 
+// The grid sizes are spread over several translation units so that they compile in
+// parallel: this file is compiled once per unit with FWR_ONCHIP_UNIT = 0 ... 4.  Unit 0
+// holds the size dispatch and the small sizes; units 1 ... 4 hold the explicit
+// instantiations of the large ones (FWR_ONCHIP_UNIT undefined: everything in one unit).
+#ifndef FWR_ONCHIP_UNIT
+#define FWR_ONCHIP_UNIT -1
+#endif
+#define FWR_ONCHIP_INST(NN)                                                                  \
+  template hipError_t launch_onchip<NN>(const OnchipArgs &, hipStream_t, int, int);        \
+  template hipError_t prepare_onchip<NN>(int, int);
+#define FWR_ONCHIP_EXTERN(NN)                                                                \
+  extern template hipError_t launch_onchip<NN>(const OnchipArgs &, hipStream_t, int, int); \
+  extern template hipError_t prepare_onchip<NN>(int, int);
+#if FWR_ONCHIP_UNIT < 0 || FWR_ONCHIP_UNIT == 1
+FWR_ONCHIP_INST(80)
+#else
+FWR_ONCHIP_EXTERN(80)
+#endif
+#if FWR_ONCHIP_UNIT < 0 || FWR_ONCHIP_UNIT == 2
+FWR_ONCHIP_INST(128)
+#else
+FWR_ONCHIP_EXTERN(128)
+#endif
+#if FWR_ONCHIP_UNIT < 0 || FWR_ONCHIP_UNIT == 3
+FWR_ONCHIP_INST(64)
+#else
+FWR_ONCHIP_EXTERN(64)
+#endif
+#if FWR_ONCHIP_UNIT < 0 || FWR_ONCHIP_UNIT == 4
+FWR_ONCHIP_INST(48)
+FWR_ONCHIP_INST(40)
+#else
+FWR_ONCHIP_EXTERN(48)
+FWR_ONCHIP_EXTERN(40)
+#endif
+
+#if FWR_ONCHIP_UNIT <= 0
+
 bool onchip_supported(int N) {
   switch (N) {
 #define FWR_CASE(NN) case NN: return true;
@@ -873,5 +911,7 @@ hipError_t onchip_launch(int N, const OnchipArgs &a, hipStream_t s, int pairs, i
     default: return hipErrorInvalidValue;
   }
 }
+
+#endif  // FWR_ONCHIP_UNIT <= 0
 
 }  // namespace fwr
