@@ -105,3 +105,30 @@ def features(slopes_grid: np.ndarray, pupil: np.ndarray, scale: float) -> np.nda
     x[:, 0:2] = slopes_grid * scale
     x[:, 2] = pupil.astype(np.float64)
     return x
+
+
+def adam_step(params, grads, state, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update (Kingma & Ba, "Adam: a method for stochastic optimization", Algorithm 1).
+
+    `params` and `grads` are flat float64 arrays of the same length; `state` is a dict that
+    holds the step count t and the first and second moment estimates m and v (empty on the
+    first call).  With t the number of the step being taken:
+        m <- beta1 m + (1 - beta1) g,       v <- beta2 v + (1 - beta2) g^2,
+        m^ = m / (1 - beta1^t),             v^ = v / (1 - beta2^t),
+        theta <- theta - lr m^ / (sqrt(v^) + eps).
+    Returns the new parameters; `state` is updated in place.
+    """
+    g = np.asarray(grads, dtype=np.float64)
+    theta = np.asarray(params, dtype=np.float64)
+    if not state:
+        state["t"] = 0
+        state["m"] = np.zeros_like(g)
+        state["v"] = np.zeros_like(g)
+    state["t"] += 1
+    t = state["t"]
+    state["m"] = beta1 * state["m"] + (1.0 - beta1) * g
+    state["v"] = beta2 * state["v"] + (1.0 - beta2) * g * g
+    m_hat = state["m"] / (1.0 - beta1 ** t)
+    v_hat = state["v"] / (1.0 - beta2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps)

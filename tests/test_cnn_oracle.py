@@ -94,3 +94,35 @@ def test_input_gradient_matches_central_differences():
 def test_parameter_count():
     n = sum(cout * cin * 9 + cout for cin, cout in C.LAYERS)
     assert n == 47714
+
+
+def test_adam_two_steps_by_hand():
+    """Adam (Kingma & Ba, Algorithm 1), values worked out by hand for two steps.
+
+    Element 0 sees g = 2 twice: the bias-corrected moments are 2 and 4 after either step, so
+    each step moves lr * 2 / (2 + eps).  Element 1 sees g = 1 then g = -1: after step 2,
+    m = 0.9 * 0.1 - 0.1 = -0.01, m^ = -0.01 / (1 - 0.81) = -1/19, v = 0.999 * 0.001 + 0.001
+    = 0.001999, v^ = 0.001999 / (1 - 0.998001) = 1, so step 2 moves +lr / 19 / (1 + eps).
+    Element 2 has g = 0 throughout and stays put.  A missing bias correction, a swapped
+    beta, or eps inside the square root would move these values well beyond the tolerance."""
+    lr, eps = 1e-3, 1e-8
+    theta0 = np.array([0.5, -0.25, 3.0])
+    state = {}
+    th1 = C.adam_step(theta0, np.array([2.0, 1.0, 0.0]), state, lr)
+    assert state["t"] == 1
+    want1 = np.array([0.5 - lr * 2 / (2 + eps), -0.25 - lr * 1 / (1 + eps), 3.0])
+    assert np.allclose(th1, want1, rtol=0, atol=1e-15)
+    th2 = C.adam_step(th1, np.array([2.0, -1.0, 0.0]), state, lr)
+    want2 = np.array([want1[0] - lr * 2 / (2 + eps), want1[1] + lr / 19 / (1 + eps), 3.0])
+    assert np.allclose(th2, want2, rtol=0, atol=1e-15)
+    # raw moments: m = 0.9 * 0.2 + 0.2 = 0.38 and v = 0.999 * 0.004 + 0.004 = 0.007996 for g = 2
+    assert np.allclose(state["m"], [0.38, -0.01, 0.0], rtol=0, atol=1e-15)
+    assert np.allclose(state["v"], [0.007996, 0.001999, 0.0], rtol=0, atol=1e-15)
+
+
+def test_adam_first_step_is_lr_times_sign():
+    """A property of Adam's first step (Kingma & Ba, Sec. 2.1): with bias correction the first
+    update has magnitude lr (up to eps) whatever the gradient's scale."""
+    g = RNG.standard_normal(50) * np.logspace(-3, 3, 50)
+    th = C.adam_step(np.zeros(50), g, {}, 0.01)
+    assert np.allclose(th, -0.01 * np.sign(g), rtol=1e-4)

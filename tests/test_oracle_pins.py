@@ -248,18 +248,102 @@ def test_zero_mask_gives_zero_output():
 
 # ------------------------------------------------------------- final filter
 
-def test_von_karman_constant_and_psd_value():
-    """Textbook von Karman PSD used for W_phi (Eq. 3); r0, L0 from Table 1 / the workload."""
+def test_von_karman_constant():
+    """Textbook von Karman constant used for W_phi (Eq. 3); r0, L0 from Table 1 / the workload."""
     from scipy.special import gamma as G
     c = (24 / 5 * G(6 / 5)) ** (5 / 6) * G(11 / 6) ** 2 / (2 * np.pi ** (11 / 3))
     assert abs(c - 0.022896) < 5e-7
-    k2 = np.array([0.0, 1.0, 4.0])
-    v = O.von_karman_psd(k2, 0.15, 25.0)
-    want = c * 0.15 ** (-5 / 3) * (k2 + 25.0 ** -2) ** (-11 / 6)
-    assert np.allclose(v, want, rtol=1e-14)
-    # Kolmogorov limit kappa >> 1/L0: 0.0229 r0^-5/3 kappa^-11/3
-    assert np.isclose(O.von_karman_psd(np.array([1e6]), 0.15, 25.0)[0],
-                      c * 0.15 ** (-5 / 3) * 1e6 ** (-11 / 6), rtol=1e-9)
+
+
+def _one_minus_j0(x: float) -> float:
+    """1 - J0(x) without cancellation: the power series of J0 for small x (the region near
+    kappa = 0 still carries weight in the structure-function integral)."""
+    from scipy.special import j0
+    if x < 0.05:
+        y = (x / 2) ** 2
+        return y - y * y / 4 + y ** 3 / 36 - y ** 4 / 576
+    return 1.0 - float(j0(x))
+
+
+def _structure_function(r: float, r0: float, L0: float) -> float:
+    """D(r) = 4 pi int_0^inf Phi(kappa) [1 - J0(2 pi kappa r)] kappa dkappa of the oracle's PSD
+    (isotropic phase, Wiener-Khinchin), by quadrature in log kappa."""
+    from scipy.integrate import quad
+
+    def f(u):
+        k = math.exp(u)
+        return float(O.von_karman_psd(np.array(k * k), r0, L0)) * _one_minus_j0(2 * math.pi * k * r) * k * k
+
+    import warnings
+    from scipy.integrate import IntegrationWarning
+    edges = np.linspace(math.log(1e-4 / L0), math.log(1e5 / r), 60)
+    with warnings.catch_warnings():  # oscillatory segments report the subdivision cap; the
+        warnings.simplefilter("ignore", IntegrationWarning)  # asserts below bound the error
+        return 4 * math.pi * sum(quad(f, a, b, limit=200, epsabs=0, epsrel=1e-10)[0]
+                                 for a, b in zip(edges[:-1], edges[1:]))
+
+
+@pytest.mark.parametrize("r0", [0.15, 0.08])
+def test_von_karman_kolmogorov_limit(r0):
+    """W_phi of Eq. 3: with an outer scale far beyond r, the PSD's phase structure function is
+    Kolmogorov's D(r) = 2 [24/5 Gamma(6/5)]^(5/6) (r / r0)^(5/3) = 6.88 (r / r0)^(5/3) (Fried's
+    definition of r0).  Fixes the constant, the -11/6 power and the r0 scaling of the PSD.  The
+    residual finite-L0 correction at L0 = 1e12 m is below 2e-4 for r <= 1 m."""
+    from scipy.special import gamma as G
+    K = 2 * (24 / 5 * G(6 / 5)) ** (5 / 6)
+    assert abs(K - 6.88) < 4e-3
+    for r in (0.01, 0.05, 0.2, 1.0):
+        ratio = _structure_function(r, r0, 1e12) / (K * (r / r0) ** (5 / 3))
+        assert abs(ratio - 1.0) < 5e-4, (r, ratio)
+
+
+@pytest.mark.parametrize("L0", [25.0, 5.0])
+def test_von_karman_structure_function_closed_form(L0):
+    """W_phi of Eq. 3 with a finite outer scale: the published closed form of the von Karman
+    phase structure function,
+      D(r) = (L0 / r0)^(5/3) 2^(1/6) Gamma(11/6) / pi^(8/3) [24/5 Gamma(6/5)]^(5/6)
+             [Gamma(5/6) / 2^(1/6) - x^(5/6) K_(5/6)(x)],  x = 2 pi r / L0,
+    matched by the oracle PSD's integral.  Fixes the (kappa^2 + L0^-2) form and the constant."""
+    from scipy.special import gamma as G, kv
+    r0 = 0.15
+    for r in (0.05, 1.0, 10.0):
+        x = 2 * math.pi * r / L0
+        want = (L0 / r0) ** (5 / 3) * 2 ** (1 / 6) * G(11 / 6) / math.pi ** (8 / 3) \
+            * (24 / 5 * G(6 / 5)) ** (5 / 6) * (G(5 / 6) / 2 ** (1 / 6) - x ** (5 / 6) * kv(5 / 6, x))
+        got = _structure_function(r, r0, L0)
+        assert abs(got / want - 1.0) < 1e-7, (r, got, want)
+
+
+def test_wiener_scale_is_bayes_optimal():
+    """Eq. 3 with gamma = 1 is the MMSE (Wiener) filter only if W_eta / W_phi is the true
+    noise-to-signal ratio of the DFT coefficients.  On periodic von Karman frames (the
+    generator's PSD on the N x N grid) with Fried slopes plus white noise, the oracle's ratio
+    must give a smaller mean error than the same ratio scaled by 1/4, 1/2, 2 or 4: a wrong
+    power of d, a missing N^2 or a wrong PSD normalisation moves the optimum off x1.  The
+    error is piston- and waffle-removed (the Fried model does not see either)."""
+    N, d, sigma, r0, L0 = 32, 0.2, 0.5, 0.15, 25.0
+    rng = np.random.default_rng(20170512)
+    Gx, Gy = O.fried_model(N)
+    ratio = O.noise_to_signal(N, d, r0, L0, sigma ** 2)
+    scales = (0.25, 0.5, 1.0, 2.0, 4.0)
+    recon = {s: O.wiener_reconstructor(Gx, Gy, 1.0, s * ratio) for s in scales}
+    err = dict.fromkeys(scales, 0.0)
+    m, n = np.indices((N, N))
+    waffle = (-1.0) ** (m + n) / N
+    for _ in range(300):
+        phi = I.vk_screen(rng, N, d, r0, L0)
+        sx, sy = D.fried_stencil_slopes(phi)
+        sx = sx + sigma * rng.standard_normal((N, N))
+        sy = sy + sigma * rng.standard_normal((N, N))
+        for s in scales:
+            e = O.fourier_reconstruct(sx, sy, *recon[s]) - phi
+            e -= e.mean()
+            e -= np.sum(e * waffle) * waffle
+            err[s] += float(np.sum(e * e))
+    best = min(err, key=err.get)
+    assert best == 1.0, {s: math.sqrt(v / (300 * N * N)) for s, v in err.items()}
+    # the optimum is not flat: the x1/4 and x4 filters are clearly worse
+    assert err[0.25] > 1.02 * err[1.0] and err[4.0] > 1.02 * err[1.0]
 
 
 def test_noise_to_signal_index_mapping():
