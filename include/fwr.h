@@ -14,9 +14,11 @@
  *   - optionally the periodicity condition of Eq. 5 (Algorithm 1 step 5);
  *   - the final Fourier reconstruction of Eq. 2 with the Wiener filter of
  *     Eq. 3 (gamma = 1 gives the MMSE filter; gamma = 0 least squares).
- * The slope model is the Fried geometry: a subaperture measures the mean of
- * the two phase differences across its four corner nodes (the discrete model
- * of Eq. 1; the paper's own sub-pixel filter is not reproduced).
+ * Two slope models (fwr_model): the Fried geometry, where a subaperture
+ * measures the mean of the two phase differences across its four corner nodes
+ * (the discrete model of Eq. 1), and the lenslet-averaging model of Eq. 4,
+ * where it measures the difference of the phase averaged over its opposite
+ * edges (transfer function with the sinc factor of Eq. 4).
  *
  * Conventions (all calls):
  *   - Row index = y, column index = x, row-major, float32, no padding.
@@ -38,6 +40,11 @@
  *     thrown across this boundary.  A kernel fault surfaces as FWR_E_DEVICE
  *     from a later call or from the caller's own stream synchronisation.
  *   - One plan may be used from one host thread at a time.
+ *   - Non-finite input: the hot path does not test values.  Frames are
+ *     transformed in pairs (frame 2i in the real part and 2i+1 in the
+ *     imaginary part of one complex field), so a NaN or infinity in a
+ *     frame's in-pupil slopes reaches the output of that frame and of its
+ *     partner in the pair; other frames are unaffected.
  */
 #ifndef FWR_H
 #define FWR_H
@@ -63,8 +70,10 @@ typedef enum {
                               difference of the phase averaged over its opposite edges;
                               transfer function exp(i pi (k'+l')/N) 2i sin(pi k'/N) sinc(l'/N)
                               (x; y transposed), signed frequencies, zero on the Nyquist row
-                              and column.  Grids N = 8, 16, 24, 32, 40, 48, 64, 80; no per-
-                              iteration Eq. 5, start values, residual or device generator. */
+                              and column.  Grids N = 8, 16, 24, 32, 40, 48, 64, 80 on chip,
+                              with start values, the residual and the Hudgin extension as for
+                              the Fried model; no per-iteration Eq. 5 and no device
+                              generator (which samples Fried slopes). */
 } fwr_model;
 
 typedef struct fwr_plan_s *fwr_plan_t;   /* opaque; owns every device table */
@@ -98,8 +107,8 @@ typedef struct {
  * geometry tables in double precision on the host, rounds them to float and
  * uploads them.  Grid sizes: N = 4 * t with t in {2,3,4,5,6,8,10,12,16,20,32}
  * (N = 8 ... 128) run on-chip (one LDS tile per frame pair); N = 256 runs as
- * grid-wide passes through a plan-owned device workspace (start values, the
- * residual and the group launch of several plans are on-chip only).  Other N
+ * grid-wide passes through a plan-owned device workspace (start values and the
+ * residual are on-chip only).  Other N
  * give FWR_E_UNSUPPORTED.  On success *out holds the plan; on failure *out is
  * set to NULL. */
 fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out);
@@ -200,8 +209,13 @@ fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ex
  * branches when `stream` is being captured into a HIP graph).  Each item is as
  * fwr_reconstruct (d_start / d_resid optional, as fwr_reconstruct_start).  A
  * plan may appear in one item only (its workspace serves one batch at a time);
- * one call at a time per process.  The first call creates the streams and
- * events (on the current device); make one call before capturing a graph.
+ * one call at a time per process.  Every item is checked before anything is
+ * enqueued (the first failing item's status; nothing runs).  The first call
+ * creates max(8, n_work) streams and events on the current device, later calls
+ * with more items add streams; a call made while `stream` is being captured
+ * that would need new streams gives FWR_E_UNSUPPORTED, so make one call with
+ * at least as many items before capturing.  After a failed launch the other
+ * branches still join `stream` (FWR_E_DEVICE).
  */
 typedef struct {
   fwr_plan_t plan;

@@ -19,6 +19,7 @@
 #include <utility>
 
 #include "cnn.h"
+#include "lds_limit.h"
 
 namespace fwr {
 namespace cnn {
@@ -391,7 +392,7 @@ hipError_t conv_prepare(int N) {
                            halo_bytes<32>(N)};
   for (int i = 0; i < 5; ++i) {
     if (bytes[i] > 160 * 1024) return hipErrorInvalidValue;
-    const hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes[i]));
+    const hipError_t e = fwr::raise_dynamic_lds(fns[i], int(bytes[i]));
     if (e != hipSuccess) return e;
   }
   hipError_t e = measure_grid(conv_kernel<8, 32, 0>, bytes[0], N);

@@ -3,6 +3,7 @@
 // (the plan tabulates the source cell of every grid cell), then Eq. 5 on the extended slopes.
 // One workgroup per frame; the frame's extended slopes are staged in LDS for the line sums.
 #include "hudgin.h"
+#include "lds_limit.h"
 
 namespace fwr {
 
@@ -62,8 +63,7 @@ __global__ __launch_bounds__(256) void hudgin_kernel(HudginArgs a) {
 size_t hudgin_lds_bytes(int N) { return (size_t)(2 * N * N + 2 * N + 8 * N) * sizeof(float); }
 
 hipError_t hudgin_prepare(int N) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&hudgin_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(hudgin_lds_bytes(N)));
+  return raise_dynamic_lds(reinterpret_cast<const void *>(&hudgin_kernel), int(hudgin_lds_bytes(N)));
 }
 
 hipError_t hudgin_launch(const HudginArgs &a, hipStream_t s) {

@@ -1,5 +1,5 @@
 // Fallback of the learned start: frames whose in-pupil residual after the network's start
-// exceeds a threshold are listed in ascending order, their measured slopes gathered into a
+// exceeds a threshold (or is not a number) are listed in ascending order, their measured slopes gathered into a
 // compact batch for the plain loop, and the plain loop's phases scattered back in place.
 #include "learned.h"
 
@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *resid,
   __syncthreads();
   for (int c0 = 0; c0 < B; c0 += kSelThreads) {
     const int i = c0 + threadIdx.x;
-    const bool f = i < B && resid[i] > threshold;
+    const bool f = i < B && !(resid[i] <= threshold);  // a NaN residual always falls back
     const uint64_t m = __ballot(f);
     if (lane == 0) wave_n[w] = __popcll(m);
     __syncthreads();

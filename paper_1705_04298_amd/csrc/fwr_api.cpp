@@ -214,12 +214,13 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
           return FWR_E_INVAL;
       }
   }
-  if (p.model == FWR_MODEL_SINC) return plan_fourier(p, out);
-  if (p.model != FWR_MODEL_FRIED) return FWR_E_UNSUPPORTED;
+  // the physical parameters of Eq. 3 feed the final filter of both slope models
   if (p.alpha_map == nullptr && p.gamma != 0.0) {
     if (!(p.gamma > 0.0) || !(p.noise_var >= 0.0) || !(p.r0 > 0.0) || !(p.L0 > 0.0) || !(p.d > 0.0))
       return FWR_E_INVAL;
   }
+  if (p.model == FWR_MODEL_SINC) return plan_fourier(p, out);
+  if (p.model != FWR_MODEL_FRIED) return FWR_E_UNSUPPORTED;
   if (fwr::multipass_supported(N)) return plan_multipass(p, out);
   if (!fwr::onchip_supported(N)) return FWR_E_UNSUPPORTED;
 
@@ -332,10 +333,9 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
   return FWR_OK;
 }
 
-static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
-                      const float *start = nullptr, float *resid = nullptr, hipStream_t stream = nullptr,
-                      bool use_stream = false) {
-  const hipStream_t st = use_stream ? stream : (valid(plan) ? plan->stream : nullptr);
+// Argument checks of one extension / reconstruction call (no device work).
+static fwr_status check_args(fwr_plan_t plan, const float *in, const float *out, int32_t B, bool extend,
+                             const float *start, const float *resid) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
@@ -345,6 +345,15 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   // outside); the extended-slope output, Eq. 5 and the residual need iterations
   if (start != nullptr && plan->n_iter == 0 && (extend || resid != nullptr || (plan->flags & fwr::kFlagPeriodic)))
     return FWR_E_INVAL;
+  return FWR_OK;
+}
+
+static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
+                      const float *start = nullptr, float *resid = nullptr, hipStream_t stream = nullptr,
+                      bool use_stream = false) {
+  if (const fwr_status c = check_args(plan, in, out, B, extend, start, resid); c != FWR_OK) return c;
+  if (B == 0) return FWR_OK;
+  const hipStream_t st = use_stream ? stream : plan->stream;
   if (plan->fourier) {
     fwr::FourierArgs a = plan->fa;
     a.slopes = in;
@@ -403,34 +412,52 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
   static std::vector<hipStream_t> pool;
   static std::vector<hipEvent_t> evs;
   if (n_work < 0 || (n_work > 0 && work == nullptr)) return FWR_E_INVAL;
+  // every item is checked before anything is enqueued
   for (int i = 0; i < n_work; ++i) {
-    if (!valid(work[i].plan)) return FWR_E_STATE;
+    const fwr_work &w = work[i];
+    if (!valid(w.plan)) return FWR_E_STATE;
     for (int k = 0; k < i; ++k)
-      if (work[k].plan == work[i].plan) return FWR_E_INVAL;  // a plan's workspace serves one item
+      if (work[k].plan == w.plan) return FWR_E_INVAL;  // a plan's workspace serves one item
+    if (const fwr_status c = check_args(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid);
+        c != FWR_OK)
+      return c;
   }
   if (n_work == 0) return FWR_OK;
   std::lock_guard<std::mutex> lock(mu);
-  while ((int)pool.size() < n_work) {
+  const hipStream_t main = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(main, &cap) != hipSuccess) return FWR_E_DEVICE;
+  // the streams and events are made outside any capture (at least 8 on the first call)
+  const int want = n_work > 8 ? n_work : 8;
+  if ((int)pool.size() < n_work && cap != hipStreamCaptureStatusNone) return FWR_E_UNSUPPORTED;
+  while ((int)pool.size() < want) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return FWR_E_DEVICE;
     pool.push_back(s);
   }
-  while ((int)evs.size() < n_work + 1) {
+  while ((int)evs.size() < want + 1) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FWR_E_DEVICE;
     evs.push_back(e);
   }
-  const hipStream_t main = static_cast<hipStream_t>(stream);
-  if (hipEventRecord(evs[n_work], main) != hipSuccess) return FWR_E_DEVICE;
+  hipEvent_t fork = evs[want];
+  if (hipEventRecord(fork, main) != hipSuccess) return FWR_E_DEVICE;
   fwr_status status = FWR_OK;
+  int forked = 0;
   for (int i = 0; i < n_work; ++i) {
-    if (hipStreamWaitEvent(pool[i], evs[n_work], 0) != hipSuccess) return FWR_E_DEVICE;
+    if (hipStreamWaitEvent(pool[i], fork, 0) != hipSuccess) {
+      status = FWR_E_DEVICE;
+      break;
+    }
+    forked = i + 1;
     const fwr_work &w = work[i];
     const fwr_status st = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, pool[i], true);
     if (st != FWR_OK && status == FWR_OK) status = st;
-    if (hipEventRecord(evs[i], pool[i]) != hipSuccess) return FWR_E_DEVICE;
-    if (hipStreamWaitEvent(main, evs[i], 0) != hipSuccess) return FWR_E_DEVICE;
   }
+  // every forked branch joins back into the caller's stream, also after a failed launch
+  for (int i = 0; i < forked; ++i)
+    if (hipEventRecord(evs[i], pool[i]) != hipSuccess || hipStreamWaitEvent(main, evs[i], 0) != hipSuccess)
+      status = FWR_E_DEVICE;
   return status;
 }
 

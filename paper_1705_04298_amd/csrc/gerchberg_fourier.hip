@@ -17,6 +17,7 @@
 // (row layout), the measured slopes of the window rows stay in LDS.
 #include "fft_lane.h"
 #include "fourier.h"
+#include "lds_limit.h"
 
 #include <cstdint>
 
@@ -267,7 +268,7 @@ hipError_t prepare_n(int n, int frames) {
   const void *fn = frames == 2 ? reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 2>)
                                : reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 1>);
   const int dyn = frames * n * fourier::Shape<N>::P * 8;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  return raise_dynamic_lds(fn, dyn);
 }
 
 template <int N>

@@ -30,6 +30,7 @@
 // reads of the inverse transform and the writes of the stencil hit the
 // thread's own slots, so they need no barrier in between.
 #include "fft_lane.h"
+#include "lds_limit.h"
 #include "onchip.h"
 
 #include <cstdint>
@@ -771,7 +772,7 @@ hipError_t prepare_pairs(int n) {
       fns[3] = reinterpret_cast<const void *>(&gerchberg_onchip_kernel<N, false, PAIRS, true, 1>);
     hipError_t e = hipSuccess;
     for (int i = 0; i < 4 && e == hipSuccess; ++i)
-      if (fns[i]) e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+      if (fns[i]) e = raise_dynamic_lds(fns[i], dyn);
     return e;
   }
 }

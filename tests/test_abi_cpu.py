@@ -80,3 +80,27 @@ def test_cnn_create_validates_on_the_host():
     assert lib.fwr_cnn_create(6, 15, mp, 1, 0.5, 0, None, ctypes.byref(h)) == F.FWR_E_INVAL       # N - n odd
     assert lib.fwr_cnn_forward(None, None, None, 1) == F.FWR_E_STATE
     assert lib.fwr_cnn_destroy(None) == F.FWR_E_STATE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfwr.so not built")
+@pytest.mark.parametrize("model", [0, 1])
+def test_plan_rejects_bad_physical_parameters_for_both_models(model):
+    """Eq. 3's W_eta / W_phi needs d > 0, r0 > 0, L0 > 0, sigma^2 >= 0 and gamma >= 0: both slope
+    models (Fried 0, lenslet averaging 1) reject other values before any device work."""
+    import numpy as np
+    from paper_1705_04298_amd import fwr as F
+    lib = F.load()
+    n, N = 40, 80
+    mask = np.ones((n, n), dtype=np.uint8)
+    good = dict(gamma=1.0, noise_var=0.0025, r0=0.15, L0=25.0, d=0.2)
+    for field, value in (("d", 0.0), ("r0", -1.0), ("L0", 0.0), ("noise_var", -1e-3), ("gamma", -1.0),
+                         ("d", float("nan"))):
+        p = F.FwrParams()
+        p.n_sub, p.n_grid, p.n_iter, p.periodic, p.max_batch, p.model = n, N, 2, 1, 1, model
+        for k, v in good.items():
+            setattr(p, k, v)
+        setattr(p, field, value)
+        p.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        h = ctypes.c_void_p()
+        assert lib.fwr_plan(ctypes.byref(p), ctypes.byref(h)) == F.FWR_E_INVAL, (model, field, value)
+        assert not h.value
