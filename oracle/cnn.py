@@ -65,13 +65,18 @@ def init_params(seed: int = 0, layers=LAYERS):
     return params
 
 
-def forward(x: np.ndarray, params):
-    """Returns the list of layer outputs (post-activation; the last is linear)."""
+def forward(x: np.ndarray, params, act_round=None):
+    """Returns the list of layer outputs (post-activation; the last is linear).
+
+    `act_round` (optional) is applied to every hidden layer's output before the next layer
+    reads it: the precision an implementation stores its activations in (None = FP64)."""
     acts = [x]
     h = x
     for li, (w, b) in enumerate(params):
         z = conv3x3(h, w, b)
         h = np.maximum(z, 0.0) if li < len(params) - 1 else z
+        if act_round is not None and li < len(params) - 1:
+            h = act_round(h)
         acts.append(h)
     return acts
 
@@ -84,14 +89,19 @@ def masked_mse(pred: np.ndarray, target: np.ndarray, outside: np.ndarray):
     return float(np.sum(diff * diff) / count), 2.0 * diff / count
 
 
-def backward(acts, params, gout: np.ndarray):
-    """Backpropagate dloss/d(output) through the network; returns [(gw, gb)] per layer."""
+def backward(acts, params, gout: np.ndarray, grad_round=None):
+    """Backpropagate dloss/d(output) through the network; returns [(gw, gb)] per layer.
+
+    `grad_round` (optional) is applied to the gradient with respect to every hidden layer's
+    pre-activation (after its ReLU), the precision an implementation stores it in."""
     grads = [None] * len(params)
     g = gout
     for li in range(len(params) - 1, -1, -1):
         w, _ = params[li]
         if li < len(params) - 1:
             g = g * (acts[li + 1] > 0.0)       # ReLU of this layer
+            if grad_round is not None:
+                g = grad_round(g)
         gx, gw, gb = conv3x3_backward(acts[li], w, g)
         grads[li] = (gw, gb)
         g = gx

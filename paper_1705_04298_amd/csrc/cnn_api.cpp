@@ -277,8 +277,9 @@ fwr_status fwr_cnn_adam_step(fwr_cnn_t c, float lr) {
   if (!c->training || !(lr > 0.f)) return FWR_E_INVAL;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   c->step += 1;
-  const float c1 = float(1.0 - std::pow(0.9, double(c->step)));
-  const float c2 = float(1.0 - std::pow(0.999, double(c->step)));
+  // bias corrections from the same (FP32) betas the moment updates use
+  const float c1 = float(1.0 - std::pow(double(b1), double(c->step)));
+  const float c2 = float(1.0 - std::pow(double(b2), double(c->step)));
   if (adam(c->w, c->g, c->m1, c->m2, (int)master_total(), lr, b1, b2, eps, c1, c2, c->stream) != hipSuccess)
     return FWR_E_DEVICE;
   return repack(c);

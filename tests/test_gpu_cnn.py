@@ -1,7 +1,9 @@
 """Learned initial extension on the GPU vs the FP64 oracles (needs an MI355X).
 
-BF16 weights/activations with FP32 accumulation: the network output and the
-gradients are compared at a relative L2 tolerance of a few 1e-2; the start-value
+BF16 weights/activations with FP32 accumulation: the network output and every
+gradient are compared element by element with the oracle fed the same BF16-rounded
+inputs, weights and stored activations (bound C_BF16 * 2^-8 * (|ref| + rms(ref)));
+Adam is compared with the oracle's step on the same gradients; the start-value
 variants of Algorithm 1 keep the 1e-5 phase tolerance of the plain path.
 """
 import sys
@@ -44,49 +46,121 @@ def _oracle_inputs(slopes, mask, N):
     return C.features(grid, P, SCALE), P
 
 
-def test_cnn_forward_matches_oracle(F):
-    _flush("[gpu] cnn forward")
-    mask = I.pupil_mask(40)
-    slopes = I.make_batch(I.SPHERE_40, 2, start=200, dtype=np.float32).astype(np.float64)
+def bf16(a):
+    """Round to bfloat16 as the kernels store values: float64 -> float32 (the kernels compute in
+    FP32), then round-to-nearest-even to the upper 16 bits; returned as float64."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _stored_params(params):
+    """The parameters as the kernels use them: BF16 weights (from the FP32 master copy), FP32 biases."""
+    return [(bf16(w), np.asarray(b, dtype=np.float32).astype(np.float64)) for w, b in params]
+
+
+# Element-wise bound between the kernels and the oracle fed the same BF16-rounded inputs,
+# weights and stored activations / gradients: |got - ref| <= C_BF16 * 2^-8 * (|ref| + rms(ref)).
+# What remains between them is the FP32 accumulation order of the MFMA sums and the rare
+# stored value whose FP32 sum lies within that rounding of a BF16 rounding boundary (one BF16
+# unit, 2^-8 relative, on that value, diluted by the next layer's sum).
+# C_BF16 = 2 for every element and 1 for 99.9 % of them: an implementation that differs from
+# the FP64-summing oracle only by summing in FP32 (same BF16 storage) reaches 1.23 units on the
+# network output of the 80 x 80 case (checked on the CPU); one unit is 2^-8 (|ref| + rms(ref)).
+C_BF16 = 2.0
+
+
+def _elementwise(got, ref, what):
+    unit = 2.0 ** -8 * (np.abs(ref) + np.sqrt(np.mean(ref * ref)))
+    r = np.abs(got - ref) / unit
+    ratio, p999 = float(r.max()), float(np.quantile(r, 0.999))
+    _flush(f"[gpu]   {what}: max |got - ref| / unit = {ratio:.3g}, 99.9 % quantile {p999:.3g}")
+    assert ratio <= C_BF16 and p999 <= 1.0, (what, ratio, p999)
+
+
+CNN_GRIDS = [(40, 80), (46, 48)]
+
+
+@pytest.mark.parametrize("n,N", CNN_GRIDS)
+def test_cnn_forward_matches_oracle(F, n, N):
+    _flush(f"[gpu] cnn forward n={n} N={N}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(2, n, seed=200 + N).astype(np.float32).astype(np.float64) * 2.0
     params = C.init_params(7)
     params = [(w, np.random.default_rng(l).standard_normal(b.shape) * 0.05) for l, (w, b) in enumerate(params)]
-    net = F.CNN(40, 80, mask, max_batch=2, input_scale=SCALE, training=False)
+    net = F.CNN(n, N, mask, max_batch=2, input_scale=SCALE, training=False)
     net.set_params(F.params_to_flat(params))
     x = torch.from_numpy(slopes.astype(np.float32)).cuda()
     pred = net.forward(x)
     torch.cuda.synchronize()
     got = pred.cpu().numpy().astype(np.float64)
-    feats, _ = _oracle_inputs(slopes, mask, 80)
-    want = C.forward(feats, params)[-1] / SCALE
-    assert rel(got, want) < 3e-2, rel(got, want)
+    feats, _ = _oracle_inputs(slopes, mask, N)
+    want = C.forward(bf16(feats), _stored_params(params), act_round=bf16)[-1] / SCALE
+    _elementwise(got, want, "network output")
     back = net.get_params()
     assert np.array_equal(back, F.params_to_flat(params))
     net.close()
 
 
-def test_cnn_gradients_match_oracle(F):
-    _flush("[gpu] cnn gradients")
-    mask = I.pupil_mask(40)
-    slopes = I.make_batch(I.SPHERE_40, 2, start=210, dtype=np.float32).astype(np.float64)
-    target = np.random.default_rng(3).standard_normal((2, 2, 80, 80))
+@pytest.mark.parametrize("n,N", CNN_GRIDS)
+def test_cnn_gradients_match_oracle(F, n, N):
+    _flush(f"[gpu] cnn gradients n={n} N={N}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(2, n, seed=210 + N).astype(np.float32).astype(np.float64) * 2.0
+    target = np.random.default_rng(3).standard_normal((2, 2, N, N)).astype(np.float32).astype(np.float64)
     params = C.init_params(11)
     params = [(w, np.random.default_rng(10 + l).standard_normal(b.shape) * 0.05) for l, (w, b) in enumerate(params)]
-    net = F.CNN(40, 80, mask, max_batch=2, input_scale=SCALE, training=True)
+    net = F.CNN(n, N, mask, max_batch=2, input_scale=SCALE, training=True)
     net.set_params(F.params_to_flat(params))
     x = torch.from_numpy(slopes.astype(np.float32)).cuda()
     tgt = torch.from_numpy(target.astype(np.float32)).cuda()
     pred = net.forward(x)
     loss = net.backward(pred, tgt)
     grads = F.flat_to_params(net.get_grads(), C.LAYERS)
-    feats, P = _oracle_inputs(slopes, mask, 80)
-    acts = C.forward(feats, params)
+    feats, P = _oracle_inputs(slopes, mask, N)
+    stored = _stored_params(params)
+    acts = C.forward(bf16(feats), stored, act_round=bf16)
     want_loss, g = C.masked_mse(acts[-1], target * SCALE, ~P)
-    want = C.backward(acts, params, g)
-    assert abs(loss - want_loss) / want_loss < 2e-2
+    want = C.backward(acts, stored, bf16(g), grad_round=bf16)
+    assert abs(loss - want_loss) <= 1e-5 * want_loss, (loss, want_loss)
     for li, ((gw, gb), (ww, wb)) in enumerate(zip(grads, want)):
-        assert rel(gw, ww) < 5e-2, (li, rel(gw, ww))
-        assert rel(gb, wb) < 5e-2, (li, rel(gb, wb))
+        _elementwise(gw, ww, f"layer {li} weight gradient")
+        _elementwise(gb, wb, f"layer {li} bias gradient")
     net.close()
+
+
+def test_adam_matches_oracle(F):
+    """Three fwr_cnn_adam_step calls on the gradients of three forward/backward passes: the FP32
+    master weights equal the oracle's Adam (Kingma & Ba) applied to the same gradients with the
+    same hyper-parameters (beta1 0.9, beta2 0.999, eps 1e-8 as FP32 values), element by element,
+    to FP32 rounding: 2^-21 of the weight (a half unit in the last place per step) plus 1e-6 of
+    the steps taken."""
+    _flush("[gpu] cnn adam vs oracle")
+    n, N = 40, 80
+    mask = I.pupil_mask(n)
+    slopes = torch.from_numpy(I.make_batch(I.SPHERE_40, 4, start=250, dtype=np.float32)).cuda()
+    plan = F.Plan(n, N, mask, n_iter=20, periodic=False, max_batch=4)
+    target = plan.extend(slopes)
+    net = F.CNN(n, N, mask, max_batch=4, input_scale=SCALE, training=True)
+    theta = F.params_to_flat(C.init_params(5)).astype(np.float64)
+    net.set_params(theta.astype(np.float32))
+    theta = theta.astype(np.float32).astype(np.float64)
+    state = {}
+    hyper = dict(beta1=float(np.float32(0.9)), beta2=float(np.float32(0.999)), eps=float(np.float32(1e-8)))
+    lr_sum = 0.0
+    for step, lr in enumerate((1e-3, 3e-3, 1e-3)):
+        net.backward(net.forward(slopes), target)
+        g = net.get_grads().astype(np.float64)
+        net.adam_step(lr)
+        theta = C.adam_step(theta, g, state, lr, **hyper)
+        lr_sum += lr
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - theta)
+        bound = 2.0 ** -21 * np.abs(theta) + 1e-6 * lr_sum  # a half unit per step, 4 units in all
+        _flush(f"[gpu]   step {step}: max err / bound = {float((err / bound).max()):.3g}")
+        assert np.all(err <= bound), (step, float((err / bound).max()))
+    net.close()
+    plan.close()
 
 
 def test_adam_steps_reduce_the_loss(F):
