@@ -308,6 +308,31 @@ fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn
                                    float *d_start, float *d_phase, float *d_resid, float threshold, int32_t B,
                                    int32_t *h_count);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): fwr_reconstruct_learned
+ * without any allocation and without waiting for the stream.  Same arguments,
+ * checks and results (bit for bit) as fwr_reconstruct_learned, except:
+ *   - the number of recomputed frames goes to d_count (DEVICE int32, may be
+ *     NULL) instead of a host variable; nothing is read back;
+ *   - the frame list and the gathered slopes and phases of the fallback live in
+ *     one fixed library workspace per GPU of FWR_NOALLOC_SCRATCH_BYTES (16 MiB,
+ *     held until the process ends), not in buffers of the fallback plan.  The
+ *     fallback runs in chunks that fit it (at most 2 * floor(S / (8 (2 n^2 +
+ *     (n+1)^2))) frames per chunk, S the workspace after the frame list), each
+ *     launch sized for a full chunk, the frames past the device-side count
+ *     exiting at once;
+ *   - B <= FWR_NOALLOC_MAX_FRAMES (FWR_E_INVAL beyond); the fallback plan must
+ *     use the Fried model (FWR_E_UNSUPPORTED otherwise).
+ * Every call on a GPU shares that GPU's workspace, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  The workspace's address is looked up once per
+ * device on the first call there (no allocation). */
+#define FWR_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define FWR_NOALLOC_MAX_FRAMES 65536
+fwr_status fwr_reconstruct_learned_noalloc(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn,
+                                           const float *d_slopes, float *d_start, float *d_phase,
+                                           float *d_resid, float threshold, int32_t B, int32_t *d_count);
+
 /* Static description of a status code (never NULL). */
 const char *fwr_status_string(int32_t status);
 

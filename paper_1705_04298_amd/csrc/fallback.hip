@@ -3,7 +3,16 @@
 // compact batch for the plain loop, and the plain loop's phases scattered back in place.
 #include "learned.h"
 
+#include <map>
+#include <mutex>
+
 namespace fwr {
+
+// Fixed device workspace of the allocation-free learned call (fwr_reconstruct_learned_noalloc):
+// the frame list, its length and one chunk of gathered slopes and phases (layout in learned.h).
+// One copy per GPU, held until the process ends.  In host code this name is not a device
+// address: the address comes from hipGetSymbolAddress (fallback_scratch) and only that is used.
+static __device__ __align__(256) unsigned char scratch[FWR_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -47,7 +56,54 @@ __global__ __launch_bounds__(256) void move_kernel(const float *src, const int32
   for (int i = threadIdx.x; i < per_frame; i += 256) d[i] = s[i];
 }
 
+// The same move for list positions off + blockIdx.x, for as many of them as the device-side list
+// length *count allows (blocks past it exit at once): the chunks of the allocation-free call.
+template <bool GATHER>
+__global__ __launch_bounds__(256) void move_counted_kernel(const float *src, const int32_t *idx, const int32_t *count,
+                                                           int off, float *dst, int per_frame) {
+  const int j = off + int(blockIdx.x);
+  if (j >= *count) return;
+  const size_t from = GATHER ? (size_t)idx[j] : blockIdx.x;
+  const size_t to = GATHER ? blockIdx.x : (size_t)idx[j];
+  const float *s = src + from * per_frame;
+  float *d = dst + to * per_frame;
+  for (int i = threadIdx.x; i < per_frame; i += 256) d[i] = s[i];
+}
+
 }  // namespace
+
+hipError_t fallback_scratch(void **ptr) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;  // device -> address of its copy of `scratch`
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    it = addr.emplace(dev, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
+}
+
+hipError_t fallback_gather_counted(const float *src, const int32_t *idx, const int32_t *count, int off, float *dst,
+                                   int blocks, int per_frame, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(move_counted_kernel<true>, dim3(blocks), dim3(256), 0, s, src, idx, count, off, dst, per_frame);
+  return hipGetLastError();
+}
+
+hipError_t fallback_scatter_counted(const float *src, const int32_t *idx, const int32_t *count, int off, float *dst,
+                                    int blocks, int per_frame, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(move_counted_kernel<false>, dim3(blocks), dim3(256), 0, s, src, idx, count, off, dst,
+                     per_frame);
+  return hipGetLastError();
+}
 
 hipError_t fallback_select(const float *resid, float threshold, int B, int32_t *idx, int32_t *count,
                            hipStream_t s) {

@@ -348,12 +348,15 @@ static fwr_status check_args(fwr_plan_t plan, const float *in, const float *out,
   return FWR_OK;
 }
 
+// `count` (device int32, on-chip plans only): the launch covers B frames of which the first
+// min(B, *count - count_off) are processed (see OnchipArgs).
 static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
                       const float *start = nullptr, float *resid = nullptr, hipStream_t stream = nullptr,
-                      bool use_stream = false) {
+                      bool use_stream = false, const int32_t *count = nullptr, int count_off = 0) {
   if (const fwr_status c = check_args(plan, in, out, B, extend, start, resid); c != FWR_OK) return c;
   if (B == 0) return FWR_OK;
   const hipStream_t st = use_stream ? stream : plan->stream;
+  if (count != nullptr && (plan->fourier || plan->multipass)) return FWR_E_UNSUPPORTED;
   if (plan->fourier) {
     fwr::FourierArgs a = plan->fa;
     a.slopes = in;
@@ -386,6 +389,8 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   a.flags = plan->flags | (extend ? fwr::kFlagExtend : 0);
   a.start = start;
   a.resid = resid;
+  a.count = count;
+  a.count_off = count_off;
   return fwr::onchip_launch(plan->N, a, st, plan->pairs, plan->sched) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
@@ -513,9 +518,12 @@ fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ex
   return fwr::hudgin_launch(a, plan->stream) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
-fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn, const float *d_slopes,
-                                   float *d_start, float *d_phase, float *d_resid, float threshold, int32_t B,
-                                   int32_t *h_count) {
+}  // extern "C"
+
+// Argument checks shared by the two learned calls (B = 0 passes; nothing is enqueued).
+static fwr_status check_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn, const float *d_slopes,
+                                const float *d_start, const float *d_phase, const float *d_resid, float threshold,
+                                int32_t B) {
   if (!valid(plan) || !valid(fallback)) return FWR_E_STATE;
   int cn = 0, cN = 0, cmax = 0;
   hipStream_t cs = nullptr;
@@ -523,13 +531,24 @@ fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn
   if (cn != plan->n || cN != plan->N || fallback->n != plan->n || fallback->N != plan->N) return FWR_E_INVAL;
   if (cs != plan->stream || fallback->stream != plan->stream) return FWR_E_INVAL;
   if (B < 0 || B > plan->max_batch || B > fallback->max_batch || B > cmax) return FWR_E_INVAL;
-  if (h_count != nullptr) *h_count = 0;
   if (B == 0) return FWR_OK;
   if (d_slopes == nullptr || d_start == nullptr || d_phase == nullptr || d_resid == nullptr ||
       std::isnan(threshold))
     return FWR_E_INVAL;
   if (plan->multipass || plan->fourier) return FWR_E_UNSUPPORTED;
   if (plan->n_iter < 1) return FWR_E_INVAL;  // the residual is that of the last iteration
+  return FWR_OK;
+}
+
+extern "C" {
+
+fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn, const float *d_slopes,
+                                   float *d_start, float *d_phase, float *d_resid, float threshold, int32_t B,
+                                   int32_t *h_count) {
+  if (h_count != nullptr) *h_count = 0;
+  if (const fwr_status c = check_learned(plan, fallback, cnn, d_slopes, d_start, d_phase, d_resid, threshold, B);
+      c != FWR_OK || B == 0)
+    return c;
   const int n = plan->n;
   const size_t per_s = (size_t)2 * n * n, per_p = (size_t)(n + 1) * (n + 1);
   if (fallback->fb_mem == nullptr) {
@@ -564,6 +583,53 @@ fwr_status fwr_reconstruct_learned(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn
       return FWR_E_DEVICE;
   }
   if (h_count != nullptr) *h_count = count;
+  return FWR_OK;
+}
+
+fwr_status fwr_reconstruct_learned_noalloc(fwr_plan_t plan, fwr_plan_t fallback, fwr_cnn_t cnn,
+                                           const float *d_slopes, float *d_start, float *d_phase, float *d_resid,
+                                           float threshold, int32_t B, int32_t *d_count) {
+  if (const fwr_status c = check_learned(plan, fallback, cnn, d_slopes, d_start, d_phase, d_resid, threshold, B);
+      c != FWR_OK)
+    return c;
+  if (B > FWR_NOALLOC_MAX_FRAMES) return FWR_E_INVAL;
+  if (fallback->fourier) return FWR_E_UNSUPPORTED;  // the chunked fallback needs the on-chip Fried kernel
+  const hipStream_t st = plan->stream;
+  void *base = nullptr;
+  if (fwr::fallback_scratch(&base) != hipSuccess) return FWR_E_DEVICE;
+  int32_t *idx = static_cast<int32_t *>(base);
+  int32_t *cnt = reinterpret_cast<int32_t *>(static_cast<char *>(base) + fwr::kNoallocCountOffset);
+  if (B == 0) {  // the select kernel of an empty batch writes the count 0 (a kernel, not a memset node)
+    if (d_count != nullptr && fwr::fallback_select(nullptr, threshold, 0, idx, d_count, st) != hipSuccess)
+      return FWR_E_DEVICE;
+    return FWR_OK;
+  }
+  const int n = plan->n;
+  const size_t per_s = (size_t)2 * n * n, per_p = (size_t)(n + 1) * (n + 1);
+  // chunk capacity: an even number of frames, so that the frames of the gathered list pair up
+  // (two frames per complex field) exactly as in the one-batch fallback
+  const size_t room = FWR_NOALLOC_SCRATCH_BYTES - fwr::kNoallocChunkOffset;
+  const int cap = int(2 * (room / (2 * (per_s + per_p) * sizeof(float))));
+  if (cap < 2) return FWR_E_UNSUPPORTED;
+  float *chunk_s = reinterpret_cast<float *>(static_cast<char *>(base) + fwr::kNoallocChunkOffset);
+  float *chunk_p = chunk_s + (size_t)cap * per_s;
+  fwr_status r = fwr_cnn_forward(cnn, d_slopes, d_start, B);
+  if (r != FWR_OK) return r;
+  r = run(plan, d_slopes, d_phase, B, false, d_start, d_resid);
+  if (r != FWR_OK) return r;
+  if (fwr::fallback_select(d_resid, threshold, B, idx, cnt, st) != hipSuccess) return FWR_E_DEVICE;
+  for (int off = 0; off < B; off += cap) {
+    const int cb = B - off < cap ? B - off : cap;
+    if (fwr::fallback_gather_counted(d_slopes, idx, cnt, off, chunk_s, cb, int(per_s), st) != hipSuccess)
+      return FWR_E_DEVICE;
+    r = run(fallback, chunk_s, chunk_p, cb, false, nullptr, nullptr, st, true, cnt, off);
+    if (r != FWR_OK) return r;
+    if (fwr::fallback_scatter_counted(chunk_p, idx, cnt, off, d_phase, cb, int(per_p), st) != hipSuccess)
+      return FWR_E_DEVICE;
+  }
+  if (d_count != nullptr &&
+      hipMemcpyAsync(d_count, cnt, sizeof(int32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return FWR_E_DEVICE;
   return FWR_OK;
 }
 

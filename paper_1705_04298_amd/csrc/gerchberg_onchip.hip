@@ -142,10 +142,17 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const int line = col;
   const int j = t & 3;
   const QuadLane q(j);
+  // frames of this launch: B, or the part of a device-side count the launch covers
+  int nb = a.B;
+  if (a.count != nullptr) {
+    const int c = *a.count - a.count_off;
+    nb = c < 0 ? 0 : (c < a.B ? c : a.B);
+    if (2 * PAIRS * int(blockIdx.x) >= nb) return;  // the whole workgroup is past the batch
+  }
   // a pair past the batch (last workgroup) computes on pair 0's input and writes nothing
-  const bool active = 2 * (PAIRS * int(blockIdx.x) + half) < a.B;
+  const bool active = 2 * (PAIRS * int(blockIdx.x) + half) < nb;
   const int fa = active ? 2 * (PAIRS * int(blockIdx.x) + half) : 0;
-  const bool hasB = active && fa + 1 < a.B;
+  const bool hasB = active && fa + 1 < nb;
   const int n = WIN ? N / 2 : a.n, o = WIN ? N / 4 : a.o;
   // with WIN: in-lane slots k whose node columns 4k + j (some lane j) meet the window
   // [o, o+n] (the support of q2), and the window plus one column either side (the

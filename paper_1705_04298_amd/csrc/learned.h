@@ -24,4 +24,17 @@ hipError_t fallback_gather(const float *src, const int32_t *idx, float *dst, int
 hipError_t fallback_scatter(const float *src, const int32_t *idx, float *dst, int count, int per_frame,
                             hipStream_t s);
 
+// Allocation-free variant.  The library's fixed device workspace (FWR_NOALLOC_SCRATCH_BYTES,
+// one per GPU) on the current device: frame list int32[FWR_NOALLOC_MAX_FRAMES] at byte 0, its
+// length at kNoallocCountOffset, the chunk buffers from kNoallocChunkOffset on.
+constexpr size_t kNoallocCountOffset = (size_t)FWR_NOALLOC_MAX_FRAMES * sizeof(int32_t);
+constexpr size_t kNoallocChunkOffset = kNoallocCountOffset + 256;
+hipError_t fallback_scratch(void **ptr);
+// Gather / scatter of list positions off .. off + blocks - 1 that lie below the device-side
+// list length *count (the other blocks exit).
+hipError_t fallback_gather_counted(const float *src, const int32_t *idx, const int32_t *count, int off, float *dst,
+                                   int blocks, int per_frame, hipStream_t s);
+hipError_t fallback_scatter_counted(const float *src, const int32_t *idx, const int32_t *count, int off, float *dst,
+                                    int blocks, int per_frame, hipStream_t s);
+
 }  // namespace fwr

@@ -21,6 +21,10 @@ struct OnchipArgs {
   const float *start;     // optional [B][2][N][N]: out-of-pupil start slopes (NULL: zeros)
   float *resid;           // optional [B]: in-pupil misfit of the last iteration
   const uint8_t *mask;    // [n][n]: 1 = valid subaperture
+  // optional device count: the batch is min(B, max(0, *count - count_off)) frames, read by the
+  // kernel (workgroups past it exit at once); NULL = B frames
+  const int32_t *count = nullptr;
+  int count_off = 0;
   int B, n, o, n_iter, flags;
 };
 

@@ -35,7 +35,7 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
             "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned", "fwr_plan_set_schedule",
-            "fwr_plan_get_schedule")
+            "fwr_plan_get_schedule", "fwr_reconstruct_learned_noalloc")
 CNN_PARAMS = 47714
 
 
@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_destroy.restype = ctypes.c_int
     lib.fwr_reconstruct_learned.argtypes = [vp, vp, vp, vp, vp, vp, vp, f32, i32, ctypes.POINTER(i32)]
     lib.fwr_reconstruct_learned.restype = ctypes.c_int
+    lib.fwr_reconstruct_learned_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, f32, i32, vp]
+    lib.fwr_reconstruct_learned_noalloc.restype = ctypes.c_int
     lib.fwr_hudgin_extend.argtypes = [vp, vp, vp, i32]
     lib.fwr_hudgin_extend.restype = ctypes.c_int
     lib.fwr_plan_set_group.argtypes = [vp, i32]
@@ -151,6 +153,15 @@ def fwr_reconstruct_learned(plan, fallback, cnn, d_slopes: int, d_start: int, d_
     return load().fwr_reconstruct_learned(plan, fallback, cnn, ctypes.c_void_p(d_slopes), ctypes.c_void_p(d_start),
                                           ctypes.c_void_p(d_phase), ctypes.c_void_p(d_resid), float(threshold),
                                           B, count)
+
+
+def fwr_reconstruct_learned_noalloc(plan, fallback, cnn, d_slopes: int, d_start: int, d_phase: int, d_resid: int,
+                                    threshold: float, B: int, d_count: int = 0) -> int:
+    """The allocation-free learned call; d_count: device int32 address or 0."""
+    return load().fwr_reconstruct_learned_noalloc(plan, fallback, cnn, ctypes.c_void_p(d_slopes),
+                                                  ctypes.c_void_p(d_start), ctypes.c_void_p(d_phase),
+                                                  ctypes.c_void_p(d_resid), float(threshold), B,
+                                                  ctypes.c_void_p(d_count or None))
 
 
 def status_string(status: int) -> str:
