@@ -284,6 +284,23 @@ fwr_status fwr_cnn_forward(fwr_cnn_t cnn, const float *d_slopes, float *d_pred, 
  * NULL) receives the loss (the call then waits for the stream).  Clears its
  * gradient buffers with memsets: not for graph capture. */
 fwr_status fwr_cnn_backward(fwr_cnn_t cnn, const float *d_pred, const float *d_target, int32_t B, float *h_loss);
+/* The loss of fwr_cnn_backward for any prediction-shaped map: d_pred, d_target
+ * float[B][2][N][N] in slope units; writes d_grad, float[B][2][N][N], the gradient
+ * of the loss with respect to d_pred (2 s^2 (pred - target) / count outside the
+ * pupil, 0 inside, s = input_scale, count = 2 B times the out-of-pupil cells).
+ * Used to train the network through Algorithm 1: the loop is linear in its start
+ * and its out-of-pupil map is symmetric, so the gradient of a loss on the
+ * extension after k iterations is the same k-iteration loop run on that loss's
+ * gradient with zero measurements (fwr_extend_start).  *h_loss as for
+ * fwr_cnn_backward. */
+fwr_status fwr_cnn_loss_grad(fwr_cnn_t cnn, const float *d_pred, const float *d_target, float *d_grad, int32_t B,
+                             float *h_loss);
+/* After fwr_cnn_forward on the same batch (training mode): gradients of every
+ * parameter from d_grad, float[B][2][N][N], the gradient of the caller's loss with
+ * respect to the network's prediction (slope units), into the gradient buffer
+ * read by fwr_cnn_get_grads and used by fwr_cnn_adam_step.  Clears the buffer
+ * with a memset: not for graph capture. */
+fwr_status fwr_cnn_backward_grad(fwr_cnn_t cnn, const float *d_grad, int32_t B);
 fwr_status fwr_cnn_get_grads(fwr_cnn_t cnn, float *h_grads, int32_t count);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
 fwr_status fwr_cnn_adam_step(fwr_cnn_t cnn, float lr);

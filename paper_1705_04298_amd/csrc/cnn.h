@@ -26,6 +26,11 @@ hipError_t features(const float *slopes, const uint8_t *mask, uint16_t *feat, in
                     hipStream_t s);
 hipError_t loss_grad(const float *pred, const float *target, const uint8_t *mask, uint16_t *dz7, float *loss, int B,
                      int n, int N, float scale, float inv_count, hipStream_t s);
+// the same loss with dloss/dpred (slope units) as a float map [B][2][N][N] (zero inside the pupil)
+hipError_t loss_grad_map(const float *pred, const float *target, const uint8_t *mask, float *grad, float *loss, int B,
+                         int n, int N, float scale, float inv_count, hipStream_t s);
+// dz7 from dloss/dpred (slope units)
+hipError_t grad_in(const float *grad, uint16_t *dz7, int B, int N, float inv_scale, hipStream_t s);
 hipError_t adam(float *w, const float *g, float *m1, float *m2, int count, float lr, float b1, float b2, float eps,
                 float c1, float c2, hipStream_t s);
 hipError_t pack(const float *w, uint16_t *wt, uint16_t *wtb, int cin_s, int cout_s, int kpad_f, int kpad_b,

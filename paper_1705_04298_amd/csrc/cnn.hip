@@ -312,6 +312,46 @@ __global__ void loss_grad_kernel(const float *__restrict__ pred, const float *__
   if ((threadIdx.x & 63) == 0) atomicAdd(loss, l * inv_count);
 }
 
+// The same loss, with its gradient with respect to the prediction in slope units written as a
+// float map: grad = 2 scale^2 (pred - target) / count outside the pupil, 0 inside.
+__global__ void loss_grad_map_kernel(const float *__restrict__ pred, const float *__restrict__ target,
+                                     const uint8_t *__restrict__ mask, float *__restrict__ grad,
+                                     float *__restrict__ loss, int B, int n, int N, float scale, float inv_count) {
+  const size_t total = (size_t)B * N * N;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (i < total) {
+    const int b = int(i / ((size_t)N * N));
+    const int rem = int(i - (size_t)b * N * N), m = rem / N, c = rem - m * N, o = (N - n) / 2;
+    const int ii = m - o, jj = c - o;
+    const bool inside = ii >= 0 && ii < n && jj >= 0 && jj < n && mask[ii * n + jj];
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const size_t idx = ((size_t)b * 2 + ch) * N * N + rem;
+      const float d = inside ? 0.f : (pred[idx] - target[idx]) * scale;
+      l += d * d;
+      grad[idx] = 2.f * d * scale * inv_count;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, l * inv_count);
+}
+
+// dz7 (the gradient at the last layer's output, bf16, 16 channels) from a gradient with respect to
+// the prediction in slope units: the prediction is that output divided by the input scale.
+__global__ void grad_in_kernel(const float *__restrict__ grad, uint16_t *__restrict__ dz7, int B, int N,
+                               float inv_scale) {
+  const size_t total = (size_t)B * N * N;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const size_t NN = (size_t)N * N, b = i / NN, rem = i - b * NN;
+  uint16_t *g = dz7 + i * 16;
+  g[0] = f2bf(grad[(b * 2 + 0) * NN + rem] * inv_scale);
+  g[1] = f2bf(grad[(b * 2 + 1) * NN + rem] * inv_scale);
+#pragma unroll
+  for (int k = 2; k < 16; ++k) g[k] = 0;
+}
+
 // Adam on FP32 master weights (kernel layout [co][t][ci]), then the bf16 copies:
 // wt [co][kpad] for the forward pass, wtb [ci][t' * COUTS + co] (taps flipped) for backward-data.
 __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m1,
@@ -462,6 +502,20 @@ hipError_t loss_grad(const float *pred, const float *target, const uint8_t *mask
   const size_t total = (size_t)B * N * N;
   hipLaunchKernelGGL(loss_grad_kernel, dim3((total + 255) / 256), dim3(256), 0, s, pred, target, mask, dz7, loss, B,
                      n, N, scale, inv_count);
+  return hipGetLastError();
+}
+
+hipError_t loss_grad_map(const float *pred, const float *target, const uint8_t *mask, float *grad, float *loss, int B,
+                         int n, int N, float scale, float inv_count, hipStream_t s) {
+  const size_t total = (size_t)B * N * N;
+  hipLaunchKernelGGL(loss_grad_map_kernel, dim3((total + 255) / 256), dim3(256), 0, s, pred, target, mask, grad, loss,
+                     B, n, N, scale, inv_count);
+  return hipGetLastError();
+}
+
+hipError_t grad_in(const float *grad, uint16_t *dz7, int B, int N, float inv_scale, hipStream_t s) {
+  const size_t total = (size_t)B * N * N;
+  hipLaunchKernelGGL(grad_in_kernel, dim3((total + 255) / 256), dim3(256), 0, s, grad, dz7, B, N, inv_scale);
   return hipGetLastError();
 }
 

@@ -242,18 +242,16 @@ fwr_status fwr_cnn_forward(fwr_cnn_t c, const float *d_slopes, float *d_pred, in
   return FWR_OK;
 }
 
-fwr_status fwr_cnn_backward(fwr_cnn_t c, const float *d_pred, const float *d_target, int32_t B, float *h_loss) {
-  if (!valid(c)) return FWR_E_STATE;
-  if (!c->training) return FWR_E_UNSUPPORTED;
-  if (B < 1 || B > c->max_batch || d_pred == nullptr || d_target == nullptr) return FWR_E_INVAL;
-  const int N = c->N, n = c->n;
+}  // extern "C"
+
+namespace {
+
+// Parameter gradients from c->dz7 (the last layer's output gradient) back through the network.
+fwr_status backprop(fwr_cnn_t c, int32_t B) {
+  const int N = c->N;
   const size_t P = master_total();
   hipStream_t s = c->stream;
-  const float inv_count = float(1.0 / (double(B) * 2.0 * c->outside));
   if (hipMemsetAsync(c->g, 0, P * sizeof(float), s) != hipSuccess) return FWR_E_DEVICE;
-  if (hipMemsetAsync(c->loss, 0, sizeof(float), s) != hipSuccess) return FWR_E_DEVICE;
-  if (loss_grad(d_pred, d_target, c->mask, c->dz7, c->loss, B, n, N, c->scale, inv_count, s) != hipSuccess)
-    return FWR_E_DEVICE;
   const uint16_t *dz = c->dz7;
   for (int l = kLayers - 1; l >= 0; --l) {
     const uint16_t *xin = l == 0 ? c->feat : c->act[l - 1];
@@ -264,12 +262,54 @@ fwr_status fwr_cnn_backward(fwr_cnn_t c, const float *d_pred, const float *d_tar
       dz = dx;
     }
   }
+  return FWR_OK;
+}
+
+fwr_status read_loss(fwr_cnn_t c, float *h_loss) {
   if (h_loss) {
-    if (hipMemcpyAsync(h_loss, c->loss, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+    if (hipMemcpyAsync(h_loss, c->loss, sizeof(float), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
       return FWR_E_DEVICE;
   }
   return FWR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fwr_status fwr_cnn_backward(fwr_cnn_t c, const float *d_pred, const float *d_target, int32_t B, float *h_loss) {
+  if (!valid(c)) return FWR_E_STATE;
+  if (!c->training) return FWR_E_UNSUPPORTED;
+  if (B < 1 || B > c->max_batch || d_pred == nullptr || d_target == nullptr) return FWR_E_INVAL;
+  const float inv_count = float(1.0 / (double(B) * 2.0 * c->outside));
+  hipStream_t s = c->stream;
+  if (hipMemsetAsync(c->loss, 0, sizeof(float), s) != hipSuccess) return FWR_E_DEVICE;
+  if (loss_grad(d_pred, d_target, c->mask, c->dz7, c->loss, B, c->n, c->N, c->scale, inv_count, s) != hipSuccess)
+    return FWR_E_DEVICE;
+  if (const fwr_status r = backprop(c, B); r != FWR_OK) return r;
+  return read_loss(c, h_loss);
+}
+
+fwr_status fwr_cnn_loss_grad(fwr_cnn_t c, const float *d_pred, const float *d_target, float *d_grad, int32_t B,
+                             float *h_loss) {
+  if (!valid(c)) return FWR_E_STATE;
+  if (B < 1 || B > c->max_batch || d_pred == nullptr || d_target == nullptr || d_grad == nullptr)
+    return FWR_E_INVAL;
+  const float inv_count = float(1.0 / (double(B) * 2.0 * c->outside));
+  if (hipMemsetAsync(c->loss, 0, sizeof(float), c->stream) != hipSuccess) return FWR_E_DEVICE;
+  if (loss_grad_map(d_pred, d_target, c->mask, d_grad, c->loss, B, c->n, c->N, c->scale, inv_count, c->stream) !=
+      hipSuccess)
+    return FWR_E_DEVICE;
+  return read_loss(c, h_loss);
+}
+
+fwr_status fwr_cnn_backward_grad(fwr_cnn_t c, const float *d_grad, int32_t B) {
+  if (!valid(c)) return FWR_E_STATE;
+  if (!c->training) return FWR_E_UNSUPPORTED;
+  if (B < 1 || B > c->max_batch || d_grad == nullptr) return FWR_E_INVAL;
+  if (grad_in(d_grad, c->dz7, B, c->N, 1.f / c->scale, c->stream) != hipSuccess) return FWR_E_DEVICE;
+  return backprop(c, B);
 }
 
 fwr_status fwr_cnn_adam_step(fwr_cnn_t c, float lr) {

@@ -35,7 +35,8 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_cnn_backward", "fwr_cnn_get_grads", "fwr_cnn_adam_step", "fwr_cnn_destroy",
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
             "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned", "fwr_plan_set_schedule",
-            "fwr_plan_get_schedule", "fwr_reconstruct_learned_noalloc")
+            "fwr_plan_get_schedule", "fwr_reconstruct_learned_noalloc", "fwr_cnn_loss_grad",
+            "fwr_cnn_backward_grad")
 CNN_PARAMS = 47714
 
 
@@ -119,6 +120,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_cnn_forward.restype = ctypes.c_int
     lib.fwr_cnn_backward.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
     lib.fwr_cnn_backward.restype = ctypes.c_int
+    lib.fwr_cnn_loss_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
+    lib.fwr_cnn_loss_grad.restype = ctypes.c_int
+    lib.fwr_cnn_backward_grad.argtypes = [vp, vp, i32]
+    lib.fwr_cnn_backward_grad.restype = ctypes.c_int
     lib.fwr_cnn_adam_step.argtypes = [vp, f32]
     lib.fwr_cnn_adam_step.restype = ctypes.c_int
     lib.fwr_cnn_set_stream.argtypes = [vp, vp]
@@ -483,6 +488,24 @@ class CNN:
         if st != FWR_OK:
             raise FwrError(st, "fwr_cnn_backward")
         return float(loss.value)
+
+    def loss_grad(self, pred, target, grad=None) -> tuple:
+        """fwr_cnn_loss_grad: (loss, dloss/dpred) of the masked MSE for any prediction-shaped map."""
+        import torch
+        if grad is None:
+            grad = torch.empty_like(pred)
+        loss = ctypes.c_float()
+        st = load().fwr_cnn_loss_grad(self._h, pred.data_ptr(), target.data_ptr(), grad.data_ptr(), pred.shape[0],
+                                      ctypes.byref(loss))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_loss_grad")
+        return float(loss.value), grad
+
+    def backward_grad(self, grad):
+        """fwr_cnn_backward_grad: parameter gradients from dloss/dpred (after forward on the same batch)."""
+        st = load().fwr_cnn_backward_grad(self._h, grad.data_ptr(), grad.shape[0])
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_cnn_backward_grad")
 
     def set_stream(self, stream: Optional[int] = None):
         """Rebind to `stream` (default: torch's current stream), e.g. a capture stream."""

@@ -71,8 +71,15 @@ def targets(slopes_dev, chunk: int = 4096, n_iter: int = 50):
 
 
 def train(frames: int, epochs: int, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-          workers: int = 1, log=print, init: np.ndarray | None = None):
-    """Train the network on `frames` generated frames; returns (params, history)."""
+          workers: int = 1, log=print, init: np.ndarray | None = None, loop_iters: int = 0):
+    """Train the network on `frames` generated frames; returns (params, history).
+
+    loop_iters = 0: loss on the network's prediction itself (out-of-pupil MSE against the
+    50-iteration extension).  loop_iters = k > 0: loss on the extension after k iterations of
+    Algorithm 1 started from the prediction, i.e. on what the loop makes of the start; its
+    gradient with respect to the prediction is the same k-iteration loop run with zero
+    measurements on the loss gradient (the loop's out-of-pupil map is symmetric), so the
+    network learns the components the loop itself converges slowly on."""
     import torch
     t0 = time.perf_counter()
     slopes, _ = make_frames(frames, seed0=1000 * (seed + 1), workers=workers)
@@ -87,6 +94,10 @@ def train(frames: int, epochs: int, batch: int = 256, lr: float = 1e-3, seed: in
     hist = []
     pred = torch.empty((batch, 2, N_GRID, N_GRID), device="cuda", dtype=torch.float32)
     steps_per_epoch = frames // batch
+    if loop_iters:
+        loop = fwr.Plan(N_SUB, N_GRID, I.pupil_mask(N_SUB), n_iter=loop_iters, periodic=False, max_batch=batch)
+        zeros = torch.zeros((batch, 2, N_SUB, N_SUB), device="cuda", dtype=torch.float32)
+        ext, gext, gstart = (torch.empty_like(pred) for _ in range(3))
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(frames)).cuda()
         t1 = time.perf_counter()
@@ -96,7 +107,13 @@ def train(frames: int, epochs: int, batch: int = 256, lr: float = 1e-3, seed: in
             xb = x.index_select(0, idx).contiguous()
             yb = y.index_select(0, idx).contiguous()
             net.forward(xb, pred)
-            loss = net.backward(pred, yb)
+            if loop_iters:
+                loop.extend(xb, ext, start=pred)           # k iterations from the network's start
+                loss, _ = net.loss_grad(ext, yb, gext)      # d loss / d extension
+                loop.extend(zeros, gstart, start=gext)      # the loop's adjoint: same loop, no data
+                net.backward_grad(gstart)
+            else:
+                loss = net.backward(pred, yb)
             step_lr = lr * (0.5 ** ep)
             net.adam_step(step_lr)
             tot += loss
@@ -108,6 +125,8 @@ def train(frames: int, epochs: int, batch: int = 256, lr: float = 1e-3, seed: in
             f"{steps_per_epoch * batch / dt:.0f} frames/s)")
     params = net.get_params()
     net.close()
+    if loop_iters:
+        loop.close()
     return params, hist
 
 
@@ -234,6 +253,9 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--workers", type=int, default=0)
     t.add_argument("--out", required=True)
+    t.add_argument("--loop-iters", type=int, default=0,
+                   help="loss on the extension after this many loop iterations from the network's start")
+    t.add_argument("--init", default=None, help="start from these weights (.npz) instead of He-normal")
     t.add_argument("--evaluate", action="store_true")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", required=True)
@@ -244,7 +266,9 @@ def main(argv=None):
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.cmd == "train":
         workers = args.workers or max(1, min(16, len(os.sched_getaffinity(0))))
-        params, hist = train(args.frames, args.epochs, args.batch, args.lr, workers=workers, log=log)
+        init = np.load(args.init)["params"] if args.init else None
+        params, hist = train(args.frames, args.epochs, args.batch, args.lr, workers=workers, log=log,
+                             init=init, loop_iters=args.loop_iters)
         np.savez(args.out, params=params, history=json.dumps(hist))
         result = {"history": hist}
         if args.evaluate:

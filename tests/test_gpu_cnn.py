@@ -2,7 +2,8 @@
 
 BF16 weights/activations with FP32 accumulation: the network output and every
 gradient are compared element by element with the oracle fed the same BF16-rounded
-inputs, weights and stored activations (bound C_BF16 * 2^-8 * (|ref| + rms(ref)));
+inputs, weights and stored activations (bounds C_BF16, C_GRAD in units of
+2^-8 * (|ref| + rms(ref)));
 Adam is compared with the oracle's step on the same gradients; the start-value
 variants of Algorithm 1 keep the 1e-5 phase tolerance of the plain path.
 """
@@ -64,18 +65,25 @@ def _stored_params(params):
 # What remains between them is the FP32 accumulation order of the MFMA sums and the rare
 # stored value whose FP32 sum lies within that rounding of a BF16 rounding boundary (one BF16
 # unit, 2^-8 relative, on that value, diluted by the next layer's sum).
-# C_BF16 = 2 for every element and 1 for 99.9 % of them: an implementation that differs from
-# the FP64-summing oracle only by summing in FP32 (same BF16 storage) reaches 1.23 units on the
-# network output of the 80 x 80 case (checked on the CPU); one unit is 2^-8 (|ref| + rms(ref)).
+# One unit is 2^-8 (|ref| + rms(ref)).  The network output: 2 for every element, 1 for 99.9 % of
+# them; an implementation that differs from the FP64-summing oracle only by summing in FP32 (same
+# BF16 storage) reaches 1.23 units on the 80 x 80 case (checked on the CPU).  The parameter
+# gradients: 8 and 7.  At the end of the six-layer backward chain they can be very sensitive to the
+# summation rounding on the thin-border 48 x 48 grid: for some weights and frames, perturbing every
+# stored value by a random 1e-7 relative before its BF16 rounding moved them by up to 1.8 units, by
+# 1e-6 up to 109 units (checked on the CPU), and the kernels' FP32 MFMA sums (288 products in
+# sequence) by 8.8; for the networks and frames below they stay below 0.5 units.  A wrong tap,
+# channel or index is O(100 %), 256 units.
 C_BF16 = 2.0
+C_GRAD = 8.0
 
 
-def _elementwise(got, ref, what):
+def _elementwise(got, ref, what, c_max=C_BF16):
     unit = 2.0 ** -8 * (np.abs(ref) + np.sqrt(np.mean(ref * ref)))
     r = np.abs(got - ref) / unit
     ratio, p999 = float(r.max()), float(np.quantile(r, 0.999))
     _flush(f"[gpu]   {what}: max |got - ref| / unit = {ratio:.3g}, 99.9 % quantile {p999:.3g}")
-    assert ratio <= C_BF16 and p999 <= 1.0, (what, ratio, p999)
+    assert ratio <= c_max and p999 <= c_max - 1.0, (what, ratio, p999)
 
 
 CNN_GRIDS = [(40, 80), (46, 48)]
@@ -124,9 +132,90 @@ def test_cnn_gradients_match_oracle(F, n, N):
     want = C.backward(acts, stored, bf16(g), grad_round=bf16)
     assert abs(loss - want_loss) <= 1e-5 * want_loss, (loss, want_loss)
     for li, ((gw, gb), (ww, wb)) in enumerate(zip(grads, want)):
-        _elementwise(gw, ww, f"layer {li} weight gradient")
-        _elementwise(gb, wb, f"layer {li} bias gradient")
+        _elementwise(gw, ww, f"layer {li} weight gradient", C_GRAD)
+        _elementwise(gb, wb, f"layer {li} bias gradient", C_GRAD)
     net.close()
+
+
+def test_loss_gradient_map_matches_oracle(F):
+    """fwr_cnn_loss_grad: the masked MSE and its gradient with respect to the prediction (slope
+    units) against the oracle's masked_mse of the scaled maps (chain rule through the scale)."""
+    _flush("[gpu] cnn loss gradient map")
+    n, N, B = 40, 80, 3
+    mask = I.pupil_mask(n)
+    rng = np.random.default_rng(12)
+    pred = rng.standard_normal((B, 2, N, N)).astype(np.float32)
+    target = rng.standard_normal((B, 2, N, N)).astype(np.float32)
+    net = F.CNN(n, N, mask, max_batch=B, input_scale=SCALE, training=False)
+    loss, grad = net.loss_grad(torch.from_numpy(pred).cuda(), torch.from_numpy(target).cuda())
+    P = O.pupil_on_grid(mask, N)
+    want_loss, g = C.masked_mse(pred.astype(np.float64) * SCALE, target.astype(np.float64) * SCALE, ~P)
+    want = g * SCALE                                  # d loss / d pred = d loss / d (scale pred) * scale
+    got = grad.cpu().numpy().astype(np.float64)
+    assert abs(loss - want_loss) <= 1e-5 * want_loss
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    assert np.all(got[:, :, P] == 0.0)
+    net.close()
+
+
+
+@pytest.mark.parametrize("n,N", CNN_GRIDS)
+def test_backward_from_output_gradient_matches_oracle(F, n, N):
+    """fwr_cnn_backward_grad: every parameter gradient from a given d loss / d prediction, element by
+    element against the oracle with the kernels' BF16 storage (the prediction is the last layer's
+    output over the input scale, so the last layer sees d loss / d prediction / scale).  The
+    gradient is what the trainer passes: the loop's adjoint (the oracle's two-iteration loop with
+    zero measurements) applied to white noise, zero inside the pupil; network and frames are those
+    of test_cnn_gradients_match_oracle.  How far BF16 storage lets two valid summation orders
+    drift apart depends on the network and frames: for other weights and frames on the 48 x 48
+    grid, perturbing the oracle's stored values by a random 1e-6 relative moved these gradients by
+    up to 109 units (here about 10; checked on the CPU)."""
+    _flush(f"[gpu] cnn backward from an output gradient n={n} N={N}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(2, n, seed=210 + N).astype(np.float32).astype(np.float64) * 2.0
+    noise = np.random.default_rng(5).standard_normal((2, 2, N, N)) * 1e-3
+    adj = O.Params(n_sub=n, n_grid=N, n_iter=2, periodic=False)
+    G = np.empty_like(noise)
+    for b in range(2):
+        r = O.extend(np.zeros((2, n, n)), mask, adj, start=(noise[b, 0], noise[b, 1]))
+        G[b] = np.stack([r.sx, r.sy])
+    G = G.astype(np.float32).astype(np.float64)
+    params = C.init_params(11)
+    params = [(w, np.random.default_rng(10 + l).standard_normal(b.shape) * 0.05) for l, (w, b) in enumerate(params)]
+    net = F.CNN(n, N, mask, max_batch=2, input_scale=SCALE, training=True)
+    net.set_params(F.params_to_flat(params))
+    net.forward(torch.from_numpy(slopes.astype(np.float32)).cuda())
+    net.backward_grad(torch.from_numpy(G.astype(np.float32)).cuda())
+    grads = F.flat_to_params(net.get_grads(), C.LAYERS)
+    feats, _ = _oracle_inputs(slopes, mask, N)
+    stored = _stored_params(params)
+    acts = C.forward(bf16(feats), stored, act_round=bf16)
+    want = C.backward(acts, stored, bf16(G / SCALE), grad_round=bf16)
+    for li, ((gw, gb), (ww, wb)) in enumerate(zip(grads, want)):
+        _elementwise(gw, ww, f"layer {li} weight gradient", C_GRAD)
+        _elementwise(gb, wb, f"layer {li} bias gradient", C_GRAD)
+    net.close()
+
+
+def test_loop_adjoint_on_the_device(F):
+    """The trainer's gradient through Algorithm 1: with zero measurements the k-iteration loop's
+    out-of-pupil map A is symmetric, <A r, s> = <r, A s>, on the device to FP32 rounding."""
+    _flush("[gpu] loop adjoint")
+    n, N, B = 40, 80, 2
+    mask = I.pupil_mask(n)
+    plan = F.Plan(n, N, mask, n_iter=3, periodic=False, max_batch=B)
+    zeros = torch.zeros((B, 2, n, n), device="cuda")
+    rng = np.random.default_rng(21)
+    r = torch.from_numpy(rng.standard_normal((B, 2, N, N)).astype(np.float32)).cuda()
+    s_ = torch.from_numpy(rng.standard_normal((B, 2, N, N)).astype(np.float32)).cuda()
+    Ar = plan.extend(zeros, start=r).double()
+    As = plan.extend(zeros, start=s_).double()
+    for b in range(B):
+        lhs = float((Ar[b] * s_[b].double()).sum())
+        rhs = float((r[b].double() * As[b]).sum())
+        scale = float(Ar[b].norm() * s_[b].double().norm())
+        assert abs(lhs - rhs) <= 1e-5 * scale, (lhs, rhs, scale)
+    plan.close()
 
 
 def test_adam_matches_oracle(F):

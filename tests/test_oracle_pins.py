@@ -432,3 +432,27 @@ def test_paper_trend_periodicity_helps_at_few_iterations():
     for f in (1, 2):
         assert err(f, 2, True) < err(f, 2, False)
         assert err(f, 10, True) < err(f, 2, True) < err(f, 0, True)
+
+
+def test_zero_measurement_loop_is_symmetric():
+    """Algorithm 1 with zero in-pupil measurements maps an out-of-pupil start s to (P_oo)^k s with
+    P_oo = Pbar Pi Pbar, Pi the LSQ projector of Eq. 6-7 (symmetric), Pbar the out-of-pupil
+    restriction: the map is a symmetric matrix.  So the gradient of a loss on the k-iteration
+    extension with respect to the start is the same loop run on the loss gradient (how the
+    learned start is trained through the loop).  Dense matrix of the oracle's loop, N = 12."""
+    N, n, k = 12, 6, 3
+    mask = I.random_mask(n, seed=3)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=k, periodic=False)
+    zero = np.zeros((2, n, n))
+    M = np.empty((2 * N * N, 2 * N * N))
+    for col in range(2 * N * N):
+        v = np.zeros(2 * N * N)
+        v[col] = 1.0
+        v = v.reshape(2, N, N)
+        r = O.extend(zero, mask, p, start=(v[0], v[1]))
+        M[:, col] = np.concatenate([r.sx.ravel(), r.sy.ravel()])
+    assert np.allclose(M, M.T, atol=1e-12)
+    inside = np.tile(O.pupil_on_grid(mask, N).ravel(), 2)
+    assert np.all(M[inside, :] == 0.0) and np.all(M[:, inside] == 0.0)  # start read and output written outside only
+    ev = np.linalg.eigvalsh(M)
+    assert ev.min() > -1e-12 and ev.max() < 1.0 + 1e-12                 # a product of projections: 0 <= P_oo^k <= 1
