@@ -101,3 +101,43 @@ def test_lsq_recovers_a_bandlimited_phase():
     Rx, Ry = O.wiener_reconstructor(Gx, Gy, 0.0, singular=O.sinc_singular_set(N))
     rec = O.fourier_reconstruct(sx, sy, Rx, Ry)
     assert np.abs(rec - (phi - phi.mean())).max() < 1e-12
+
+
+def test_sinc_floor_is_the_nyquist_content():
+    """Why the lenslet-averaging model's open-loop error floor lies above the Fried model's on the
+    same screens: its transfer function vanishes on the Nyquist row and column (R18), so the
+    reconstruction has no content there.  Noiseless frames, a 40 x 40 square aperture padded to
+    80 x 80, screens periodic on the grid (so generator and model agree), 50 iterations.  Per
+    frame, the sinc error against the true phase is the root sum of squares of its error against
+    the truth without Nyquist lines and of the Nyquist-line content itself; over the frames (median)
+    the error against the Nyquist-free truth matches the Fried model's error against the truth."""
+    from paper_1705_04298_amd import inputs as I
+    N, n = 80, 40
+    rows = []
+    for idx in range(8):
+        scr = I.vk_screen(np.random.default_rng([7, idx]), N, 0.2, 0.15, 25.0)
+        F = np.fft.fft2(scr)
+        F[N // 2, :] = 0.0
+        F[:, N // 2] = 0.0
+        nyq_free = np.real(np.fft.ifft2(F))[:n + 1, :n + 1]
+        truth = scr[:n + 1, :n + 1]
+
+        def err(ph, ref):
+            e = ph - ref
+            e = e - e.mean()
+            return float(np.sqrt(np.mean(e * e)))
+
+        out = {}
+        for model in ("fried", "sinc"):
+            sx, sy = I.fried_slopes_from_nodes(truth) if model == "fried" else I.sinc_slopes_from_screen(scr, n)
+            p = O.Params(n_sub=n, n_grid=N, n_iter=50, periodic=True, gamma=1.0, noise_var=1e-6,
+                         r0=0.15, L0=25.0, d=0.2, model=model)
+            out[model] = O.reconstruct(np.stack([sx, sy]), np.ones((n, n), np.uint8), p)
+        s, sn = err(out["sinc"], truth), err(out["sinc"], nyq_free)
+        q = err(truth, nyq_free)                               # Nyquist-line content of the truth
+        assert abs(s - np.hypot(sn, q)) < 0.1 * s, (idx, s, sn, q)
+        assert q > 0.75 * s                                    # most of the sinc error
+        rows.append((err(out["fried"], truth), s, sn))
+    f, s, sn = np.median(np.array(rows), axis=0)
+    assert s > 1.5 * f
+    assert abs(sn - f) < 0.25 * f, (sn, f)
