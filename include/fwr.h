@@ -101,6 +101,12 @@ typedef struct {
                                otherwise); copied at plan time */
   int32_t max_batch;        /* largest B accepted by the calls, >= 1 */
   void *stream;             /* hipStream_t for every call; NULL = the null stream */
+  double d_px;              /* FWR_MODEL_SINC: length of one detector pixel [m], 0 <= d_px < d
+                               (the remark after Eq. 4: the edge-average difference is taken
+                               over d - d_px; the two edge averages lie (d - d_px) apart, each
+                               over the full edge, giving sin(pi k' (1 - d_px/d) / N) in place
+                               of sin(pi k' / N)).  0 = no correction; must be 0 for the Fried
+                               model (FWR_E_UNSUPPORTED), FWR_E_INVAL outside the range. */
 } fwr_params;
 
 /* Create a plan: validates the parameters, builds the filter, twiddle and

@@ -91,7 +91,7 @@ def fried_model(N: int):
     return Gx, Gy
 
 
-def sinc_model(N: int):
+def sinc_model(N: int, delta: float = 0.0):
     """Fourier transfer functions of the lenslet-averaging model of Eq. 4 (sinc reading).
 
     A subaperture measures the difference of the phase averaged over its two opposite
@@ -103,14 +103,20 @@ def sinc_model(N: int):
     the roles of k' and l'.  The slopes of a real phase must be real, so the transfer
     function is the Hermitian part of this expression on the DFT grid; it equals the
     expression off the Nyquist lines and vanishes on them (even N), where the expression is
-    anti-Hermitian.  The pixel-size correction d - d_px of the paper is not modelled.
+    anti-Hermitian.
+
+    Pixel-size correction (the remark after Eq. 4: the difference is effectively taken over
+    d - d_px): with delta = d_px / d the two edge averages lie (1 - delta) d apart, centred on
+    the lenslet, each still averaged over the full edge length d, and the measurement stays a
+    phase difference in radians:
+        G_x = exp(i pi (k' + l') / N) 2i sin(pi k' (1 - delta) / N) sinc(l' / N).
     """
     l, k = frequency_indices(N)
     ks = np.where(k < (N + 1) // 2, k, k - N).astype(np.float64)
     ls = np.where(l < (N + 1) // 2, l, l - N).astype(np.float64)
     shift = np.exp(1j * np.pi * (ks + ls) / N)
-    Gx = shift * 2j * np.sin(np.pi * ks / N) * np.sinc(ls / N)
-    Gy = shift * 2j * np.sin(np.pi * ls / N) * np.sinc(ks / N)
+    Gx = shift * 2j * np.sin(np.pi * ks * (1.0 - delta) / N) * np.sinc(ls / N)
+    Gy = shift * 2j * np.sin(np.pi * ls * (1.0 - delta) / N) * np.sinc(ks / N)
     if N % 2 == 0:
         nyq = (l == N // 2) | (k == N // 2)
         Gx = np.where(nyq, 0.0, Gx)
@@ -129,13 +135,15 @@ def sinc_singular_set(N: int) -> np.ndarray:
     return S
 
 
-def slope_model(name: str, N: int):
-    """(G_x, G_y, singular set) of the named model: "fried" or "sinc"."""
+def slope_model(name: str, N: int, delta: float = 0.0):
+    """(G_x, G_y, singular set) of the named model: "fried" or "sinc" (delta = d_px / d)."""
     if name == "fried":
+        if delta != 0.0:
+            raise ValueError("the pixel-size correction belongs to the lenslet-averaging model")
         Gx, Gy = fried_model(N)
         return Gx, Gy, singular_set(N)
     if name == "sinc":
-        Gx, Gy = sinc_model(N)
+        Gx, Gy = sinc_model(N, delta)
         return Gx, Gy, sinc_singular_set(N)
     raise ValueError(f"unknown slope model {name!r}")
 
@@ -363,10 +371,11 @@ class Params(NamedTuple):
     L0: float = 25.0
     d: float = 0.2
     model: str = "fried"   # slope model: "fried" or "sinc"
+    d_px: float = 0.0      # detector pixel length [m] (sinc model: difference over d - d_px)
 
 
 def final_filters(p: Params):
-    Gx, Gy, S = slope_model(p.model, p.n_grid)
+    Gx, Gy, S = slope_model(p.model, p.n_grid, p.d_px / p.d)
     ratio = None
     if p.gamma != 0.0:
         ratio = noise_to_signal(p.n_grid, p.d, p.r0, p.L0, p.noise_var)
@@ -376,7 +385,7 @@ def final_filters(p: Params):
 def extend(slopes: np.ndarray, mask: np.ndarray, p: Params, start=None) -> GerchbergResult:
     """Padded measurement -> Algorithm 1 (steps 1-5) -> extended slopes on the N x N grid."""
     s0x, s0y, P = padded_measurement(slopes, mask, p.n_grid)
-    Gx, Gy, S = slope_model(p.model, p.n_grid)
+    Gx, Gy, S = slope_model(p.model, p.n_grid, p.d_px / p.d)
     Rx, Ry = wiener_reconstructor(Gx, Gy, 0.0, singular=S)
     return gerchberg(s0x, s0y, P, Gx, Gy, Rx, Ry, p.n_iter, p.periodic,
                      p.periodic_each_iter, start)

@@ -214,6 +214,12 @@ fwr_status fwr_plan(const fwr_params *params, fwr_plan_t *out) {
           return FWR_E_INVAL;
       }
   }
+  // pixel-size correction of the lenslet-averaging model: 0 <= d_px < d (sinc model only)
+  if (!(p.d_px >= 0.0) || !std::isfinite(p.d_px)) return FWR_E_INVAL;
+  if (p.d_px > 0.0) {
+    if (p.model != FWR_MODEL_SINC) return FWR_E_UNSUPPORTED;
+    if (!(p.d > 0.0) || !(p.d_px < p.d)) return FWR_E_INVAL;
+  }
   // the physical parameters of Eq. 3 feed the final filter of both slope models
   if (p.alpha_map == nullptr && p.gamma != 0.0) {
     if (!(p.gamma > 0.0) || !(p.noise_var >= 0.0) || !(p.r0 > 0.0) || !(p.L0 > 0.0) || !(p.d > 0.0))
@@ -865,17 +871,18 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
 namespace {
 
 // Lenslet-averaging (sinc) model of Eq. 4 at DFT index (l, k): the Hermitian part of
-// exp(i pi (k' + l') / N) 2i sin(pi k' / N) sinc(l' / N) (x) and its transpose (y), signed
-// k', l'; zero on the Nyquist row and column of an even grid.
-void sinc_g(int l, int k, int N, std::complex<double> &gx, std::complex<double> &gy) {
+// exp(i pi (k' + l') / N) 2i sin(pi k' (1 - delta) / N) sinc(l' / N) (x) and its transpose (y),
+// signed k', l'; zero on the Nyquist row and column of an even grid.  delta = d_px / d: the edge
+// averages lie (1 - delta) d apart (the pixel-size correction remarked after Eq. 4).
+void sinc_g(int l, int k, int N, double delta, std::complex<double> &gx, std::complex<double> &gy) {
   gx = gy = 0.0;
   if (N % 2 == 0 && (l == N / 2 || k == N / 2)) return;
   const double ks = k < (N + 1) / 2 ? k : k - N, ls = l < (N + 1) / 2 ? l : l - N;
   auto sinc = [](double u) { return u == 0.0 ? 1.0 : std::sin(kPi * u) / (kPi * u); };
   const std::complex<double> shift = std::polar(1.0, kPi * (ks + ls) / N);
   const std::complex<double> two_i(0.0, 2.0);
-  gx = shift * two_i * std::sin(kPi * ks / N) * sinc(ls / N);
-  gy = shift * two_i * std::sin(kPi * ls / N) * sinc(ks / N);
+  gx = shift * two_i * std::sin(kPi * ks * (1.0 - delta) / N) * sinc(ls / N);
+  gy = shift * two_i * std::sin(kPi * ls * (1.0 - delta) / N) * sinc(ks / N);
 }
 
 bool sinc_singular(int l, int k, int N) {
@@ -898,7 +905,7 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
       for (int k2 = 0; k2 < T; ++k2) {
         const int l = k2 + T * beta[jj];      // y-frequency of this slot
         std::complex<double> gx, gy;
-        sinc_g(l, kf, N, gx, gy);
+        sinc_g(l, kf, N, p.d_px / p.d, gx, gy);
         const double g2 = std::norm(gx) + std::norm(gy);
         double al = 0.0;
         std::complex<double> be = 0.0, fa = 0.0, fb = 0.0;

@@ -57,6 +57,7 @@ class FwrParams(ctypes.Structure):
         ("alpha_map", ctypes.POINTER(ctypes.c_double)),
         ("max_batch", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("d_px", ctypes.c_double),
     ]
 
 
@@ -249,7 +250,7 @@ class Plan:
                  periodic_each_iter: bool = False, gamma: float = 1.0, noise_var: float = 0.05 ** 2,
                  r0: float = 0.15, L0: float = 25.0, d: float = 0.2,
                  alpha_map: Optional[np.ndarray] = None, max_batch: int = 4096,
-                 stream: Optional[int] = None, model: str = "fried"):
+                 stream: Optional[int] = None, model: str = "fried", d_px: float = 0.0):
         mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if mask.shape != (n_sub, n_sub):
             raise ValueError(f"mask must be {n_sub}x{n_sub}")
@@ -270,6 +271,7 @@ class Plan:
                        if self._alpha is not None else None)
         p.max_batch = self.max_batch
         p.stream = self.stream
+        p.d_px = float(d_px)
         self._h = fwr_plan(p)
 
     def _check(self, t, shape, name):

@@ -112,7 +112,7 @@ def fried_slopes_from_nodes(phi: np.ndarray):
     return sx, sy
 
 
-def sinc_slopes_from_screen(screen: np.ndarray, n: int):
+def sinc_slopes_from_screen(screen: np.ndarray, n: int, delta: float = 0.0):
     """Lenslet-averaged slopes (Eq. 4: the difference of the phase averaged over opposite
     lenslet edges) of the periodic ``M x M`` screen, for the ``n x n`` lenslets whose corner
     nodes are screen samples [0, n] x [0, n].
@@ -120,14 +120,16 @@ def sinc_slopes_from_screen(screen: np.ndarray, n: int):
     Computed on the screen's own grid: a screen mode exp(2 pi i (k' x + l' y) / M) (signed
     k', l') has the x measurement exp(i pi (k' + l') / M) 2i sin(pi k' / M) sinc(l' / M)
     times its value at the lenslet's first corner, y likewise; Nyquist components, whose
-    measurement of a real screen is not real, are dropped.  Returns (sx, sy), each n x n.
+    measurement of a real screen is not real, are dropped.  With delta = d_px / d the edge
+    averages lie (1 - delta) d apart (pixel-size correction): sin(pi k' (1 - delta) / M).
+    Returns (sx, sy), each n x n.
     """
     M = screen.shape[0]
     f = np.fft.fftfreq(M) * M                  # signed integer frequencies
     fx, fy = np.meshgrid(f, f)                 # fx along columns (x), fy along rows (y)
     shift = np.exp(1j * np.pi * (fx + fy) / M)
-    hx = shift * 2j * np.sin(np.pi * fx / M) * np.sinc(fy / M)
-    hy = shift * 2j * np.sin(np.pi * fy / M) * np.sinc(fx / M)
+    hx = shift * 2j * np.sin(np.pi * fx * (1.0 - delta) / M) * np.sinc(fy / M)
+    hy = shift * 2j * np.sin(np.pi * fy * (1.0 - delta) / M) * np.sinc(fx / M)
     if M % 2 == 0:
         nyq = (np.abs(fx) == M // 2) | (np.abs(fy) == M // 2)
         hx[nyq] = 0.0
@@ -150,6 +152,7 @@ class Workload:
     screen_size: int = 256     # M, periodic screen side in samples of pitch d
     config_id: int = 1
     model: str = "fried"       # slope measurement: "fried" (corner differences) or "sinc" (Eq. 4)
+    d_px_frac: float = 0.0     # sinc model: detector pixel length / lenslet pitch (d - d_px remark)
 
     @property
     def d(self) -> float:
@@ -185,7 +188,7 @@ def make_frame(w: Workload, index: int, noise_sigma: Optional[float] = None,
     scr = vk_screen(rng, w.screen_size, w.d, r0v, w.L0)
     phi = scr[: n + 1, : n + 1].copy()
     if w.model == "sinc":
-        sx, sy = sinc_slopes_from_screen(scr, n)
+        sx, sy = sinc_slopes_from_screen(scr, n, w.d_px_frac)
     else:
         sx, sy = fried_slopes_from_nodes(phi)
     noise = rng.standard_normal((2, n, n)) * sig

@@ -104,3 +104,22 @@ def test_plan_rejects_bad_physical_parameters_for_both_models(model):
         h = ctypes.c_void_p()
         assert lib.fwr_plan(ctypes.byref(p), ctypes.byref(h)) == F.FWR_E_INVAL, (model, field, value)
         assert not h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfwr.so not built")
+def test_pixel_size_correction_is_checked():
+    """d_px (the d - d_px remark after Eq. 4) belongs to the lenslet-averaging model: 0 <= d_px < d
+    there; any non-zero value on a Fried plan is unsupported.  No device work on these paths."""
+    import numpy as np
+    from paper_1705_04298_amd import fwr as F
+    lib = F.load()
+    n, N = 40, 80
+    mask = np.ones((n, n), dtype=np.uint8)
+    for model, d_px, want in ((1, -0.01, F.FWR_E_INVAL), (1, 0.2, F.FWR_E_INVAL), (1, 0.3, F.FWR_E_INVAL),
+                              (1, float("nan"), F.FWR_E_INVAL), (0, 0.02, F.FWR_E_UNSUPPORTED)):
+        p = F.FwrParams()
+        p.n_sub, p.n_grid, p.n_iter, p.periodic, p.max_batch, p.model = n, N, 2, 1, 1, model
+        p.gamma, p.noise_var, p.r0, p.L0, p.d, p.d_px = 1.0, 0.0025, 0.15, 25.0, 0.2, d_px
+        p.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        h = ctypes.c_void_p()
+        assert lib.fwr_plan(ctypes.byref(p), ctypes.byref(h)) == want, (model, d_px)

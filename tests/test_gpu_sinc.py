@@ -29,7 +29,7 @@ def _flush(msg):
 
 def _plan(F, p: O.Params, mask, B):
     return F.Plan(p.n_sub, p.n_grid, mask, n_iter=p.n_iter, periodic=p.periodic, gamma=p.gamma,
-                  noise_var=p.noise_var, r0=p.r0, L0=p.L0, d=p.d, max_batch=B, model="sinc")
+                  noise_var=p.noise_var, r0=p.r0, L0=p.L0, d=p.d, max_batch=B, model="sinc", d_px=p.d_px)
 
 
 def _rel(got, want):
@@ -48,6 +48,28 @@ def test_sphere40_sinc_matches_oracle(F, n_iter, periodic):
         want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
         assert _rel(got[b], want) <= 1e-5, (b, _rel(got[b], want))
     plan.close()
+
+
+@pytest.mark.parametrize("n_iter,periodic", [(10, True), (3, False)])
+def test_sphere40_sinc_pixel_size_correction(F, n_iter, periodic):
+    """The d - d_px correction (Table 1: 6 pixels per lenslet, d_px = d / 6) on frames measured with
+    it, against the oracle; the plan without the correction gives a different phase."""
+    import dataclasses
+    _flush(f"[gpu] sinc 40x40 with d_px = d/6, it={n_iter} periodic={periodic}")
+    mask = I.pupil_mask(40)
+    w = dataclasses.replace(I.SPHERE_40_SINC, d_px_frac=1.0 / 6.0)
+    slopes = I.make_batch(w, 4, dtype=np.float32)
+    p = O.Params(n_sub=40, n_grid=80, n_iter=n_iter, periodic=periodic, model="sinc", d=0.2, d_px=0.2 / 6.0)
+    plan = _plan(F, p, mask, 4)
+    x = torch.from_numpy(slopes).cuda()
+    got = plan.reconstruct(x).cpu().numpy().astype(np.float64)
+    for b in range(4):
+        want = O.reconstruct(slopes[b].astype(np.float64), mask, p)
+        assert _rel(got[b], want) <= 1e-5, (b, _rel(got[b], want))
+    plain = _plan(F, O.Params(n_sub=40, n_grid=80, n_iter=n_iter, periodic=periodic, model="sinc"), mask, 4)
+    assert _rel(plain.reconstruct(x).cpu().numpy().astype(np.float64), got) > 1e-3
+    plan.close()
+    plain.close()
 
 
 @pytest.mark.parametrize("N,n", [(8, 4), (16, 8), (24, 12), (32, 16), (40, 20), (48, 24), (64, 32), (80, 78)])

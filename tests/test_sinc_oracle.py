@@ -141,3 +141,51 @@ def test_sinc_floor_is_the_nyquist_content():
     f, s, sn = np.median(np.array(rows), axis=0)
     assert s > 1.5 * f
     assert abs(sn - f) < 0.25 * f, (sn, f)
+
+
+def _quadrature_slopes_dpx(kp, lp, N, m, n, delta):
+    """As _quadrature_slopes with the edge averages (1 - delta) apart, centred on the lenslet."""
+    t, w = np.polynomial.legendre.leggauss(40)
+    u = 0.5 * (t + 1.0)
+    w = 0.5 * w
+    mode = lambda x, y: np.exp(2j * np.pi * (kp * x + lp * y) / N)
+    a, b = 0.5 * delta, 1.0 - 0.5 * delta
+    sx = np.sum(w * (mode(n + b, m + u) - mode(n + a, m + u)))
+    sy = np.sum(w * (mode(n + u, m + b) - mode(n + u, m + a)))
+    return sx, sy
+
+
+@pytest.mark.parametrize("N,delta", [(16, 1.0 / 6.0), (20, 0.25)])
+def test_pixel_size_correction_matches_quadrature(N, delta):
+    """The d - d_px remark after Eq. 4: the difference of the two edge averages taken (d - d_px)
+    apart (Table 1's 6 pixels per lenslet: d_px = d / 6), each over the full edge, by
+    Gauss-Legendre quadrature of single Fourier modes."""
+    Gx, Gy = O.sinc_model(N, delta)
+    rng = np.random.default_rng(N + 1)
+    half = N // 2
+    for _ in range(12):
+        kp, lp = rng.integers(-half + 1, half, size=2)
+        m, n = rng.integers(0, N, size=2)
+        sx, sy = _quadrature_slopes_dpx(kp, lp, N, m, n, delta)
+        node = np.exp(2j * np.pi * (kp * n + lp * m) / N)
+        assert abs(sx - Gx[lp % N, kp % N] * node) < 1e-12
+        assert abs(sy - Gy[lp % N, kp % N] * node) < 1e-12
+    # delta = 0 is the model without the correction; the singular set does not change
+    assert np.array_equal(O.sinc_model(N, 0.0)[0], O.sinc_model(N)[0])
+    g2 = np.abs(Gx) ** 2 + np.abs(Gy) ** 2
+    S = O.sinc_singular_set(N)
+    assert np.all(g2[S] == 0.0) and np.all(g2[~S] > 1e-6)
+
+
+def test_pixel_size_correction_of_the_input_generator():
+    """The generator's lenslet-averaged slopes with the correction equal the model applied to a
+    screen periodic on the grid (single-mode consistency of inputs.sinc_slopes_from_screen)."""
+    from paper_1705_04298_amd import inputs as I
+    N, n, delta = 32, 16, 1.0 / 6.0
+    scr = I.vk_screen(np.random.default_rng(3), N, 0.2, 0.15, 25.0)
+    sx, sy = I.sinc_slopes_from_screen(scr, n, delta)
+    Gx, Gy = O.sinc_model(N, delta)
+    F = np.fft.fft2(scr)
+    wx = np.real(np.fft.ifft2(Gx * F))[:n, :n]
+    wy = np.real(np.fft.ifft2(Gy * F))[:n, :n]
+    assert np.allclose(sx, wx, atol=1e-12) and np.allclose(sy, wy, atol=1e-12)
