@@ -70,10 +70,11 @@ typedef enum {
                               difference of the phase averaged over its opposite edges;
                               transfer function exp(i pi (k'+l')/N) 2i sin(pi k'/N) sinc(l'/N)
                               (x; y transposed), signed frequencies, zero on the Nyquist row
-                              and column.  Grids N = 8, 16, 24, 32, 40, 48, 64, 80 on chip,
-                              with start values, the residual and the Hudgin extension as for
-                              the Fried model; no per-iteration Eq. 5 and no device
-                              generator (which samples Fried slopes). */
+                              and column; the d - d_px correction via fwr_params.d_px.
+                              Grids N = 8, 16, 24, 32, 40, 48, 64, 80, 128 on chip, with
+                              start values, the residual, per-iteration Eq. 5 and the Hudgin
+                              extension as for the Fried model; no device generator (which
+                              samples Fried slopes). */
 } fwr_model;
 
 typedef struct fwr_plan_s *fwr_plan_t;   /* opaque; owns every device table */

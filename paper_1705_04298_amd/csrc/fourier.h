@@ -8,7 +8,7 @@
 
 namespace fwr {
 
-enum : int { kFourierPeriodic = 1, kFourierExtend = 4 };
+enum : int { kFourierPeriodic = 1, kFourierPeriodicEach = 2, kFourierExtend = 4 };
 
 struct FourierArgs {
   const float *slopes;     // [B][2][n][n]

@@ -370,7 +370,9 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.start = start;
     a.resid = resid;
     a.B = B;
-    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) | (extend ? fwr::kFourierExtend : 0);
+    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) |
+              ((plan->flags & fwr::kFlagPeriodicEach) ? fwr::kFourierPeriodicEach : 0) |
+              (extend ? fwr::kFourierExtend : 0);
     return fwr::fourier_launch(plan->N, a, st, plan->frames) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
   if (plan->multipass) {
@@ -891,7 +893,7 @@ bool sinc_singular(int l, int k, int N) {
 
 fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
-  if (!fwr::fourier_supported(N) || p.periodic_each_iter) return FWR_E_UNSUPPORTED;
+  if (!fwr::fourier_supported(N)) return FWR_E_UNSUPPORTED;
   if (!fwr::fourier_frames_ok(N, n, 1)) return FWR_E_UNSUPPORTED;
   const int T = N / 4, threads = fwr::fourier_threads(N, 1);
   static const int beta[4] = {0, 2, 1, 3};
@@ -992,7 +994,7 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   plan->N = N;
   plan->o = o;
   plan->n_iter = p.n_iter;
-  plan->flags = p.periodic ? fwr::kFlagPeriodic : 0;
+  plan->flags = (p.periodic ? fwr::kFlagPeriodic : 0) | (p.periodic_each_iter ? fwr::kFlagPeriodicEach : 0);
   plan->max_batch = p.max_batch;
   plan->stream = static_cast<hipStream_t>(p.stream);
   plan->d_mem = mem;

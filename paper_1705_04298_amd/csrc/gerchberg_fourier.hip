@@ -1,5 +1,5 @@
 // Fourier-domain Gerchberg extension + reconstruction for slope models without a compact
-// real-space stencil (the lenslet-averaging model of Eq. 4), padded grids N <= 80.
+// real-space stencil (the lenslet-averaging model of Eq. 4), padded grids N <= 128.
 //
 // One frame per complex field: Z = TF(s_x + i s_y).  With X = TF(s_x), Y = TF(s_y) and
 // Z~ = conj(Z(-l, -k)), X = (Z + Z~) / 2 and Y = (Z - Z~) / (2i), so step 2 of Algorithm 1
@@ -14,7 +14,8 @@
 //
 // Layout and line transforms as in the on-chip Fried kernel (4 lanes per grid line, LDS tile
 // N x (N+1) complex per frame); the state between iterations is s_x + i s_y in registers
-// (row layout), the measured slopes of the window rows stay in LDS.
+// (row layout).  The measured slopes of the window rows stay in LDS for N <= 80; at N = 128 the
+// tile alone takes 132 KB, and step 4 reads them from global memory (L2-resident) instead.
 #include "fft_lane.h"
 #include "fourier.h"
 #include "lds_limit.h"
@@ -30,6 +31,7 @@ struct Shape {
   static constexpr int THREADS = 4 * N;
   static constexpr int P = N + 1;
   static constexpr int TILE = N * P;
+  static constexpr bool MEAS_IN_LDS = N <= 80;  // measured window rows kept in LDS
 };
 
 // FR frames per workgroup (see the on-chip kernel: N = 80 makes 5 waves per frame)
@@ -39,7 +41,8 @@ struct FGroup {
   static constexpr int WAVES = (THREADS + 63) / 64;
   static constexpr int WAVES_PER_SIMD = (WAVES + 3) / 4 > 2 ? (WAVES + 3) / 4 : 2;
   static constexpr int STATIC_LDS_BYTES = FR * (Shape<N>::TILE + 2 * N) * 8 + Shape<N>::T * 4 * 8;
-  static int lds_bytes(int n) { return STATIC_LDS_BYTES + FR * n * Shape<N>::P * 8; }
+  static int dyn_bytes(int n) { return Shape<N>::MEAS_IN_LDS ? FR * n * Shape<N>::P * 8 : 0; }
+  static int lds_bytes(int n) { return STATIC_LDS_BYTES + dyn_bytes(n); }
 };
 
 __device__ __forceinline__ float select_bits(bool c, float a, float b) {
@@ -61,7 +64,7 @@ void fourier_kernel(FourierArgs a) {
   const int t = int(threadIdx.x) - half * TH;
   float2 *const buf = buf_all + half * TILE;
   float2 *const sums = sums_all + half * N;
-  float2 *const meas = meas_all + half * a.n * P;
+  float2 *const meas = meas_all + (Shape<N>::MEAS_IN_LDS ? half * a.n * P : 0);
   const int line = t >> 2, j = t & 3;
   const QuadLane q(j);
   const bool active = FR * int(blockIdx.x) + half < a.B;  // frames past the batch write nothing
@@ -75,7 +78,7 @@ void fourier_kernel(FourierArgs a) {
   // all loads of a chunk are issued before its LDS stores (cells outside the window read
   // cell 0 and are replaced by zeros): one memory latency per chunk, not per element
   constexpr int CH = (N / 2 * N + TH - 1) / TH;
-  for (int i0 = t; i0 < n * N; i0 += CH * TH) {
+  for (int i0 = t; Shape<N>::MEAS_IN_LDS && i0 < n * N; i0 += CH * TH) {
     float vx[CH], vy[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
@@ -96,13 +99,24 @@ void fourier_kernel(FourierArgs a) {
   const uint32_t pup = a.inpupil[t];
   const bool in_rows = line >= o && line < o + n;
   const int mrow = (in_rows ? line - o : 0) * P + T * j;
+  // measured s_x + i s_y of cell (line, 4k + j) (any value outside the window; only in-pupil
+  // cells are used): from LDS, or from global memory where the LDS cannot hold the rows
+  auto meas_at = [&](int k) -> float2 {
+    if constexpr (Shape<N>::MEAS_IN_LDS) {
+      return meas[mrow + k];
+    } else {
+      const int c = 4 * k + j - o;
+      const int g = in_rows && c >= 0 && c < n ? (line - o) * n + c : 0;
+      return make_float2(sf[g], sf[plane + g]);
+    }
+  };
 
   float2 x[T];  // s_x + i s_y of cells (line, 4k + j): the measurement, zeros or the start outside
   const float *stf = a.start ? a.start + (size_t)f * 2 * N * N + (size_t)line * N + j : nullptr;
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     const bool in = in_rows && ((pup >> k) & 1u);
-    const float2 v = meas[mrow + k];
+    const float2 v = meas_at(k);
     const float ox = stf ? stf[4 * k] : 0.f, oy = stf ? stf[N * N + 4 * k] : 0.f;
     x[k] = make_float2(select_bits(in, v.x, ox), select_bits(in, v.y, oy));
   }
@@ -157,6 +171,30 @@ void fourier_kernel(FourierArgs a) {
     line_fft_inv<T>(x, tw, j, q);
   };
 
+  // Eq. 5: s_x(m, N-1) -= R_m (row sum of s_x), s_y(N-1, n) -= C_n (column sum of s_y)
+  auto eq5 = [&]() {
+    float rs = 0.f;
+#pragma unroll
+    for (int k = 0; k < T; ++k) rs += x[k].x;
+    rs += dpp_xor1(rs);
+    rs += dpp_xor2(rs);
+#pragma unroll
+    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];  // own slots: no hazard
+    __syncthreads();
+    if (t < N) {  // fixed-order column sums
+      const int slot = T * (t & 3) + (t >> 2);
+      float cs = 0.f;
+      for (int m = 0; m < N; ++m) cs += buf[m * P + slot].y;
+      sums[t] = make_float2(0.f, cs);
+    }
+    __syncthreads();
+    if (j == 3) x[T - 1].x -= rs;
+    if (line == N - 1) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) x[k].y -= sums[4 * k + j].y;
+    }
+    __syncthreads();  // the column sums are read before the next use of the buffers
+  };
   if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) a.resid[f] = 0.f;
   for (int it = 0; it < a.n_iter; ++it) {
     solve(false);
@@ -166,7 +204,7 @@ void fourier_kernel(FourierArgs a) {
 #pragma unroll
       for (int k = 0; k < T; ++k) {
         const bool in = in_rows && ((pup >> k) & 1u);
-        const float2 v = meas[mrow + k];
+        const float2 v = meas_at(k);
         const float dx = x[k].x - v.x, dy = x[k].y - v.y;
         num += in ? dx * dx + dy * dy : 0.f;
         den += in ? v.x * v.x + v.y * v.y : 0.f;
@@ -191,34 +229,13 @@ void fourier_kernel(FourierArgs a) {
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       const bool in = in_rows && ((pup >> k) & 1u);
-      const float2 v = meas[mrow + k];
+      const float2 v = meas_at(k);
       x[k] = make_float2(select_bits(in, v.x, x[k].x), select_bits(in, v.y, x[k].y));
     }
+    if (a.flags & kFourierPeriodicEach) eq5();
   }
 
-  if (a.flags & kFourierPeriodic) {
-    // Eq. 5: s_x(m, N-1) -= R_m (row sum of s_x), s_y(N-1, n) -= C_n (column sum of s_y)
-    float rs = 0.f;
-#pragma unroll
-    for (int k = 0; k < T; ++k) rs += x[k].x;
-    rs += dpp_xor1(rs);
-    rs += dpp_xor2(rs);
-#pragma unroll
-    for (int k = 0; k < T; ++k) buf[line * P + T * j + k] = x[k];  // own slots: no hazard
-    __syncthreads();
-    if (t < N) {  // fixed-order column sums
-      const int slot = T * (t & 3) + (t >> 2);
-      float cs = 0.f;
-      for (int m = 0; m < N; ++m) cs += buf[m * P + slot].y;
-      sums[t] = make_float2(0.f, cs);
-    }
-    __syncthreads();
-    if (j == 3) x[T - 1].x -= rs;
-    if (line == N - 1) {
-#pragma unroll
-      for (int k = 0; k < T; ++k) x[k].y -= sums[4 * k + j].y;
-    }
-  }
+  if (a.flags & kFourierPeriodic) eq5();
 
   if (a.flags & kFourierExtend) {
     if (active) {
@@ -247,7 +264,7 @@ void fourier_kernel(FourierArgs a) {
 
 }  // namespace fourier
 
-#define FWR_FOURIER_SIZES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80)
+#define FWR_FOURIER_SIZES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(128)
 
 namespace {
 
@@ -256,31 +273,46 @@ int lds_of(int n) {
   return fourier::FGroup<N, FR>::lds_bytes(n);
 }
 
+// two frames per workgroup only where both tiles fit the LDS (not at N = 128)
+template <int N>
+constexpr bool two_frames_instantiated() {
+  return 8 * N <= 1024 && fourier::FGroup<N, 2>::STATIC_LDS_BYTES <= 160 * 1024;
+}
+
 template <int N>
 bool frames_ok_n(int n, int frames) {
   if (frames == 1) return lds_of<N, 1>(n) <= 160 * 1024;
-  if (frames == 2) return 8 * N <= 1024 && lds_of<N, 2>(n) <= 160 * 1024;
+  if constexpr (two_frames_instantiated<N>()) {
+    if (frames == 2) return lds_of<N, 2>(n) <= 160 * 1024;
+  }
   return false;
 }
 
 template <int N>
 hipError_t prepare_n(int n, int frames) {
-  const void *fn = frames == 2 ? reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 2>)
-                               : reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 1>);
-  const int dyn = frames * n * fourier::Shape<N>::P * 8;
-  return raise_dynamic_lds(fn, dyn);
+  if constexpr (two_frames_instantiated<N>()) {
+    if (frames == 2)
+      return raise_dynamic_lds(reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 2>),
+                               fourier::FGroup<N, 2>::dyn_bytes(n));
+  }
+  if (frames != 1) return hipErrorInvalidValue;
+  return raise_dynamic_lds(reinterpret_cast<const void *>(&fourier::fourier_kernel<N, 1>),
+                           fourier::FGroup<N, 1>::dyn_bytes(n));
 }
 
 template <int N>
 hipError_t launch_n(const FourierArgs &a, hipStream_t s, int frames) {
   const int groups = (a.B + frames - 1) / frames;
-  const size_t dyn = size_t(frames) * a.n * fourier::Shape<N>::P * 8;
-  if (frames == 2)
-    hipLaunchKernelGGL((fourier::fourier_kernel<N, 2>), dim3(groups), dim3(fourier::FGroup<N, 2>::THREADS), dyn, s,
-                       a);
-  else
-    hipLaunchKernelGGL((fourier::fourier_kernel<N, 1>), dim3(groups), dim3(fourier::FGroup<N, 1>::THREADS), dyn, s,
-                       a);
+  if constexpr (two_frames_instantiated<N>()) {
+    if (frames == 2) {
+      hipLaunchKernelGGL((fourier::fourier_kernel<N, 2>), dim3(groups), dim3(fourier::FGroup<N, 2>::THREADS),
+                         size_t(fourier::FGroup<N, 2>::dyn_bytes(a.n)), s, a);
+      return hipGetLastError();
+    }
+  }
+  if (frames != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fourier::fourier_kernel<N, 1>), dim3(groups), dim3(fourier::FGroup<N, 1>::THREADS),
+                     size_t(fourier::FGroup<N, 1>::dyn_bytes(a.n)), s, a);
   return hipGetLastError();
 }
 
@@ -308,7 +340,7 @@ int fourier_threads(int N, int frames) { return 4 * N * frames; }
 
 int fourier_lds_bytes(int N, int n, int frames) {
   switch (N) {
-#define FWR_CASE(NN) case NN: return frames == 2 ? lds_of<NN, 2>(n) : lds_of<NN, 1>(n);
+#define FWR_CASE(NN) case NN: return frames == 1 ? lds_of<NN, 1>(n) : frames_ok_n<NN>(n, frames) ? lds_of<NN, 2>(n) : 0;
     FWR_FOURIER_SIZES(FWR_CASE)
 #undef FWR_CASE
     default: return 0;

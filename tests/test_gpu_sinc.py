@@ -29,7 +29,8 @@ def _flush(msg):
 
 def _plan(F, p: O.Params, mask, B):
     return F.Plan(p.n_sub, p.n_grid, mask, n_iter=p.n_iter, periodic=p.periodic, gamma=p.gamma,
-                  noise_var=p.noise_var, r0=p.r0, L0=p.L0, d=p.d, max_batch=B, model="sinc", d_px=p.d_px)
+                  noise_var=p.noise_var, r0=p.r0, L0=p.L0, d=p.d, max_batch=B, model="sinc", d_px=p.d_px,
+                  periodic_each_iter=p.periodic_each_iter)
 
 
 def _rel(got, want):
@@ -72,7 +73,8 @@ def test_sphere40_sinc_pixel_size_correction(F, n_iter, periodic):
     plain.close()
 
 
-@pytest.mark.parametrize("N,n", [(8, 4), (16, 8), (24, 12), (32, 16), (40, 20), (48, 24), (64, 32), (80, 78)])
+@pytest.mark.parametrize("N,n", [(8, 4), (16, 8), (24, 12), (32, 16), (40, 20), (48, 24), (64, 32), (80, 78),
+                                 (128, 64), (128, 126)])
 def test_sinc_grid_sizes_and_groups(F, N, n):
     _flush(f"[gpu] sinc grid N={N} n={n}")
     mask = I.random_mask(n, seed=700 + N + n)
@@ -121,8 +123,6 @@ def test_sinc_unsupported_calls(F):
         plan.generate(2, 1)
     with pytest.raises(F.FwrError):
         F.Plan(128, 256, I.pupil_mask(128), max_batch=1, model="sinc")
-    with pytest.raises(F.FwrError):
-        F.Plan(40, 80, mask, periodic_each_iter=True, max_batch=1, model="sinc")
     plan.close()
 
 
@@ -184,3 +184,53 @@ def test_sinc_hudgin_extension(F, n, N):
         assert np.array_equal(ext[b, 1, :N - 1, :], ry[:N - 1, :])
         assert _rel(phase[b], O.reconstruct_hudgin(slopes[b].astype(np.float64), mask, p)) <= 1e-5
     plan0.close()
+
+
+@pytest.mark.parametrize("N,n,periodic", [(80, 40, False), (80, 40, True), (48, 46, True), (128, 64, True)])
+def test_sinc_eq5_after_every_iteration(F, N, n, periodic):
+    """Eq. 5 after every step 4 (plan flag periodic_each_iter) under the lenslet-averaging model:
+    phase, extended slopes (measured slopes bit for bit) and residual against the oracle."""
+    _flush(f"[gpu] sinc per-iteration Eq. 5 N={N} n={n} periodic={periodic}")
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(3, n, seed=900 + N + n).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=4, periodic=periodic, periodic_each_iter=True, d=8.0 / n,
+                 model="sinc")
+    plan = _plan(F, p, mask, 3)
+    x = torch.from_numpy(slopes).cuda()
+    resid = torch.empty(3, device="cuda")
+    ext = plan.extend(x, resid=resid).cpu().numpy().astype(np.float64)
+    got = plan.reconstruct(x).cpu().numpy().astype(np.float64)
+    r = resid.cpu().numpy()
+    o = (N - n) // 2
+    for b in range(3):
+        s64 = slopes[b].astype(np.float64)
+        ref = O.extend(s64, mask, p)
+        scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+        assert np.abs(ext[b, 0] - ref.sx).max() <= 1e-4 * scale
+        assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
+        inside = mask.astype(bool)
+        assert np.array_equal(ext[b, 0, o:o + n, o:o + n][inside], slopes[b, 0][inside].astype(np.float64))
+        assert abs(r[b] - ref.residuals[-1]) <= 1e-4 * ref.residuals[-1]
+        assert _rel(got[b], O.reconstruct(s64, mask, p)) <= 1e-5
+    plan.close()
+
+
+def test_sinc_128_start_values_and_residual(F):
+    """N = 128 (measured slopes read from global memory at step 4): start values and residual."""
+    _flush("[gpu] sinc N=128 start values")
+    N, n = 128, 64
+    mask = I.pupil_mask(n)
+    slopes = I.random_slopes(2, n, seed=77).astype(np.float32)
+    start = np.random.default_rng(78).standard_normal((2, 2, N, N)).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=N, n_iter=3, periodic=True, d=39.0 / 128, model="sinc")
+    plan = _plan(F, p, mask, 2)
+    x = torch.from_numpy(slopes).cuda()
+    resid = torch.empty(2, device="cuda")
+    got = plan.reconstruct(x, start=torch.from_numpy(start).cuda(), resid=resid).cpu().numpy().astype(np.float64)
+    r = resid.cpu().numpy()
+    for b in range(2):
+        st = (start[b, 0].astype(np.float64), start[b, 1].astype(np.float64))
+        s64 = slopes[b].astype(np.float64)
+        assert _rel(got[b], O.reconstruct(s64, mask, p, start=st)) <= 1e-5
+        assert abs(r[b] - O.extend(s64, mask, p, start=st).residuals[-1]) <= 1e-4 * r[b]
+    plan.close()
