@@ -73,8 +73,10 @@ typedef enum {
                               and column; the d - d_px correction via fwr_params.d_px.
                               Grids N = 8, 16, 24, 32, 40, 48, 64, 80, 128 on chip, with
                               start values, the residual, per-iteration Eq. 5 and the Hudgin
-                              extension as for the Fried model; no device generator (which
-                              samples Fried slopes). */
+                              extension as for the Fried model; N = 256 as passes through a
+                              plan-owned workspace (Eq. 5 after the loop or every iteration;
+                              no start values, residual or Hudgin extension); no device
+                              generator (which samples Fried slopes). */
 } fwr_model;
 
 typedef struct fwr_plan_s *fwr_plan_t;   /* opaque; owns every device table */

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwr.so")
 # (source, extra define): the on-chip kernel file is compiled once per group of grid sizes
-SOURCES = [("gerchberg_onchip.hip", f"FWR_ONCHIP_UNIT={u}") for u in range(5)] + ["gerchberg_multipass.hip", "gerchberg_fourier.hip", "gen_screens.hip", "ext_hudgin.hip",
+SOURCES = [("gerchberg_onchip.hip", f"FWR_ONCHIP_UNIT={u}") for u in range(5)] + ["gerchberg_multipass.hip", "gerchberg_fourier.hip", "gerchberg_fourier_mp.hip", "gen_screens.hip", "ext_hudgin.hip",
            "cnn.hip", "fallback.hip", "fwr_api.cpp", "cnn_api.cpp"]
 ARCH = "gfx950"
 

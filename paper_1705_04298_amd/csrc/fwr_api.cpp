@@ -16,6 +16,7 @@
 #include <tuple>
 
 #include "fourier.h"
+#include "fourier_mp.h"
 #include "gen.h"
 #include "hudgin.h"
 #include "learned.h"
@@ -51,6 +52,8 @@ struct fwr_plan_s {
   // Fourier-domain path (slope models without a compact stencil)
   bool fourier = false;
   fwr::FourierArgs fa{};
+  bool fourier_mp = false;  // the Fourier-domain path through HBM (N = 256)
+  fwr::FSArgs fs{};
   int frames = 1;  // frames per workgroup of the Fourier-domain kernel
   // multi-pass path (N = 256)
   bool multipass = false;
@@ -346,7 +349,7 @@ static fwr_status check_args(fwr_plan_t plan, const float *in, const float *out,
   if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
   if (B == 0) return FWR_OK;
   if (in == nullptr || out == nullptr) return FWR_E_INVAL;
-  if ((start != nullptr || resid != nullptr) && plan->multipass) return FWR_E_UNSUPPORTED;
+  if ((start != nullptr || resid != nullptr) && (plan->multipass || plan->fourier_mp)) return FWR_E_UNSUPPORTED;
   // with no iteration the start is the extension itself: Eq. 2/3 of (measurement inside, start
   // outside); the extended-slope output, Eq. 5 and the residual need iterations
   if (start != nullptr && plan->n_iter == 0 && (extend || resid != nullptr || (plan->flags & fwr::kFlagPeriodic)))
@@ -363,6 +366,15 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
   if (B == 0) return FWR_OK;
   const hipStream_t st = use_stream ? stream : plan->stream;
   if (count != nullptr && (plan->fourier || plan->multipass)) return FWR_E_UNSUPPORTED;
+  if (plan->fourier_mp) {
+    fwr::FSArgs a = plan->fs;
+    a.slopes = in;
+    a.out = out;
+    a.B = B;
+    a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) |
+              ((plan->flags & fwr::kFlagPeriodicEach) ? fwr::kFourierPeriodicEach : 0);
+    return fwr::fourier_mp_run(a, extend, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
+  }
   if (plan->fourier) {
     fwr::FourierArgs a = plan->fa;
     a.slopes = in;
@@ -650,9 +662,9 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes) {
   if (!valid(plan)) return FWR_E_STATE;
-  if (plan->multipass) {
+  if (plan->multipass || plan->fourier_mp) {
     if (threads) *threads = 256;
-    if (frames_per_group) *frames_per_group = 2;
+    if (frames_per_group) *frames_per_group = plan->multipass ? 2 : 1;
     if (lds_bytes) *lds_bytes = 0;
     return FWR_OK;
   }
@@ -671,6 +683,7 @@ fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *fram
 fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (plan->multipass) return frames_per_group == 2 ? FWR_OK : FWR_E_UNSUPPORTED;
+  if (plan->fourier_mp) return frames_per_group == 1 ? FWR_OK : FWR_E_UNSUPPORTED;
   if (plan->fourier) {
     if (frames_per_group < 1) return FWR_E_INVAL;
     if (!fwr::fourier_frames_ok(plan->N, plan->n, frames_per_group)) return FWR_E_UNSUPPORTED;
@@ -704,8 +717,8 @@ fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule) {
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 1 || B > plan->max_batch) return FWR_E_INVAL;
-  if (plan->multipass) {
-    if (frames_per_group) *frames_per_group = 2;
+  if (plan->multipass || plan->fourier_mp) {
+    if (frames_per_group) *frames_per_group = plan->multipass ? 2 : 1;
     return FWR_OK;
   }
   const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
@@ -891,13 +904,124 @@ bool sinc_singular(int l, int k, int N) {
   return (l == 0 && k == 0) || (N % 2 == 0 && (l == N / 2 || k == N / 2));
 }
 
+// Packed-projector coefficients of the sinc model at DFT index (l, k), 1 / N^2 of the
+// unnormalised inverse transforms folded in: the loop's Z' = alpha Z + beta conj(Z(-l, -k))
+// (alpha = (a + b) / 2 + Im c, beta = (a - b) / 2 + i Re c with a = |G_x|^2 / |G|^2,
+// b = |G_y|^2 / |G|^2, c = G_x conj(G_y) / |G|^2), and the final A Z + B conj(Z(-l, -k))
+// (A, B = (R_x -/+ i R_y) / 2, R = G* / (|G|^2 + gamma W_eta / W_phi), Eq. 3).
+void sinc_coeffs(const fwr_params &p, int l, int k, float &alpha, float2 &beta, float2 &fin_a, float2 &fin_b) {
+  const int N = p.n_grid;
+  const double inv = 1.0 / (double(N) * double(N));
+  std::complex<double> gx, gy;
+  sinc_g(l, k, N, p.d_px / p.d, gx, gy);
+  const double g2 = std::norm(gx) + std::norm(gy);
+  double al = 0.0;
+  std::complex<double> be = 0.0, fa = 0.0, fb = 0.0;
+  if (!sinc_singular(l, k, N)) {
+    const double a = std::norm(gx) / g2, b = std::norm(gy) / g2;
+    const std::complex<double> cc = gx * std::conj(gy) / g2;
+    al = 0.5 * (a + b) + cc.imag();
+    be = std::complex<double>(0.5 * (a - b), cc.real());
+  }
+  const double den = g2 + regulariser(p, l, k);
+  if (den > 0.0 && !(p.gamma == 0.0 && p.alpha_map == nullptr && sinc_singular(l, k, N))) {
+    const std::complex<double> rx = std::conj(gx) / den, ry = std::conj(gy) / den;
+    const std::complex<double> I(0.0, 1.0);
+    fa = 0.5 * (rx - I * ry);
+    fb = 0.5 * (rx + I * ry);
+  }
+  alpha = float(al * inv);
+  beta = make_float2(float(be.real() * inv), float(be.imag() * inv));
+  fin_a = make_float2(float(fa.real() * inv), float(fa.imag() * inv));
+  fin_b = make_float2(float(fb.real() * inv), float(fb.imag() * inv));
+}
+
+// Multi-pass plan of the sinc model (N = 256): coefficient tables [column position][row
+// position] in the digit-reversed order the 256-point line transforms leave, and the workspace
+fwr_status plan_fourier_mp(const fwr_params &p, fwr_plan_t *out) {
+  const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
+  auto freq = [](int pos) { return (pos >> 4) + 16 * (pos & 15); };
+  const size_t NNs = (size_t)N * N;
+  std::vector<float> alpha(NNs);
+  std::vector<float2> betat(NNs), fin_a(NNs), fin_b(NNs);
+  for (int c = 0; c < N; ++c)
+    for (int q = 0; q < N; ++q) {
+      const size_t i = (size_t)c * N + q;
+      sinc_coeffs(p, freq(q), freq(c), alpha[i], betat[i], fin_a[i], fin_b[i]);
+    }
+  std::vector<float2> tw(N);
+  for (int e = 0; e < N; ++e) {
+    const double ang = -2.0 * kPi * double(e) / double(N);
+    tw[e] = make_float2(float(std::cos(ang)), float(std::sin(ang)));
+  }
+  std::vector<uint8_t> mask((size_t)n * n);
+  for (size_t i = 0; i < mask.size(); ++i) mask[i] = p.mask[i] ? 1 : 0;
+  auto *plan = new (std::nothrow) fwr_plan_s();
+  if (plan == nullptr) return FWR_E_NOMEM;
+  if (hipGetDevice(&plan->device) != hipSuccess) {
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t b_a = NNs * sizeof(float), b_c = NNs * sizeof(float2), b_tw = tw.size() * sizeof(float2);
+  const size_t off_b = b_a, off_fa = off_b + b_c, off_fb = off_fa + b_c, off_tw = off_fb + b_c;
+  const size_t off_mask = off_tw + b_tw, off_ws = (off_mask + mask.size() + 255) & ~size_t(255);
+  const size_t ws = fwr::fourier_mp_workspace_bytes(N, p.max_batch);
+  char *mem = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&mem), off_ws + ws) != hipSuccess) {
+    delete plan;
+    return FWR_E_NOMEM;
+  }
+  hipError_t e = hipMemcpy(mem, alpha.data(), b_a, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_b, betat.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_fa, fin_a.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_fb, fin_b.data(), b_c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    delete plan;
+    return FWR_E_DEVICE;
+  }
+  const size_t B = (size_t)p.max_batch;
+  char *w = mem + off_ws;
+  fwr::FSArgs &a = plan->fs;
+  a.spec = reinterpret_cast<float2 *>(w);
+  a.state = reinterpret_cast<float2 *>(w + B * NNs * sizeof(float2));
+  a.rsum = reinterpret_cast<float *>(w + 2 * B * NNs * sizeof(float2));
+  a.cpart = a.rsum + B * N;
+  a.alpha = reinterpret_cast<const float *>(mem);
+  a.beta = reinterpret_cast<const float2 *>(mem + off_b);
+  a.fin_a = reinterpret_cast<const float2 *>(mem + off_fa);
+  a.fin_b = reinterpret_cast<const float2 *>(mem + off_fb);
+  a.tw256 = reinterpret_cast<const float2 *>(mem + off_tw);
+  a.mask = reinterpret_cast<const uint8_t *>(mem + off_mask);
+  a.n = n;
+  a.o = o;
+  a.n_iter = p.n_iter;
+  plan->magic = kMagic;
+  plan->n = n;
+  plan->N = N;
+  plan->o = o;
+  plan->n_iter = p.n_iter;
+  plan->flags = (p.periodic ? fwr::kFlagPeriodic : 0) | (p.periodic_each_iter ? fwr::kFlagPeriodicEach : 0);
+  plan->max_batch = p.max_batch;
+  plan->stream = static_cast<hipStream_t>(p.stream);
+  plan->d_mem = mem;
+  plan->fourier = true;
+  plan->fourier_mp = true;
+  plan->dmask = a.mask;
+  plan->d = p.d;
+  *out = plan;
+  return FWR_OK;
+}
+
 fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
   const int n = p.n_sub, N = p.n_grid, o = (N - n) / 2;
+  if (fwr::fourier_mp_supported(N)) return plan_fourier_mp(p, out);
   if (!fwr::fourier_supported(N)) return FWR_E_UNSUPPORTED;
   if (!fwr::fourier_frames_ok(N, n, 1)) return FWR_E_UNSUPPORTED;
   const int T = N / 4, threads = fwr::fourier_threads(N, 1);
   static const int beta[4] = {0, 2, 1, 3};
-  const double inv = 1.0 / (double(N) * double(N));
   std::vector<float> alpha((size_t)T * threads);
   std::vector<float2> betat((size_t)T * threads), fin_a((size_t)T * threads), fin_b((size_t)T * threads);
   for (int c = 0; c < N; ++c) {
@@ -906,28 +1030,7 @@ fwr_status plan_fourier(const fwr_params &p, fwr_plan_t *out) {
       const size_t base = (size_t)(4 * c + jj) * T;
       for (int k2 = 0; k2 < T; ++k2) {
         const int l = k2 + T * beta[jj];      // y-frequency of this slot
-        std::complex<double> gx, gy;
-        sinc_g(l, kf, N, p.d_px / p.d, gx, gy);
-        const double g2 = std::norm(gx) + std::norm(gy);
-        double al = 0.0;
-        std::complex<double> be = 0.0, fa = 0.0, fb = 0.0;
-        if (!sinc_singular(l, kf, N)) {
-          const double a = std::norm(gx) / g2, b = std::norm(gy) / g2;
-          const std::complex<double> cc = gx * std::conj(gy) / g2;
-          al = 0.5 * (a + b) + cc.imag();
-          be = std::complex<double>(0.5 * (a - b), cc.real());
-        }
-        const double den = g2 + regulariser(p, l, kf);
-        if (den > 0.0 && !(p.gamma == 0.0 && p.alpha_map == nullptr && sinc_singular(l, kf, N))) {
-          const std::complex<double> rx = std::conj(gx) / den, ry = std::conj(gy) / den;
-          const std::complex<double> I(0.0, 1.0);
-          fa = 0.5 * (rx - I * ry);
-          fb = 0.5 * (rx + I * ry);
-        }
-        alpha[base + k2] = float(al * inv);
-        betat[base + k2] = make_float2(float(be.real() * inv), float(be.imag() * inv));
-        fin_a[base + k2] = make_float2(float(fa.real() * inv), float(fa.imag() * inv));
-        fin_b[base + k2] = make_float2(float(fb.real() * inv), float(fb.imag() * inv));
+        sinc_coeffs(p, l, kf, alpha[base + k2], betat[base + k2], fin_a[base + k2], fin_b[base + k2]);
       }
     }
   }

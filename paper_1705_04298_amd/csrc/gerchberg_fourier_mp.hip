@@ -1,0 +1,274 @@
+// Multi-pass Fourier-domain Gerchberg extension + reconstruction for the lenslet-averaging model
+// of Eq. 4 at N = 256 (a 256 x 256 complex field is 512 KiB, over the LDS).
+//
+// One frame per complex field, Z = TF(s_x + i s_y), with step 2 of Algorithm 1 as
+// Z' = alpha Z + beta conj(Z(-l, -k)) and the final reconstruction as A Z + B conj(Z(-l, -k))
+// (see gerchberg_fourier.hip), split into grid-wide passes through a per-frame spectrum field:
+//   rows : the inverse row FFTs of the spectrum, step 4 (the measurement inside the pupil) and
+//          the forward row FFTs of the next iteration, 16 rows per block, in one pass (the model
+//          has no real-space stencil, so no halo rows); or the same ending in the real-space
+//          slopes with their Eq. 5 sums; or the start, the Eq. 5 fix, the outputs;
+//   cols : forward column FFTs, the packed projector, inverse column FFTs.  Each block takes 16
+//          column positions closed under k -> -k, so the mirrored frequency is in its LDS.  The
+//          row FFTs leave frequency a + 16 b at position 16 a + b; the mirror of position
+//          16 a + b is 16 (16 - a) + 15 - b (a > 0) or (16 - b) mod 16 (a = 0): position groups
+//          a and 16 - a pair up, groups 0 and 8 are closed.  A block takes 8 contiguous
+//          positions of group a and their 8 (contiguous) mirrors, or all of group 0 or 8.
+#include "fft256.h"
+#include "fourier.h"
+#include "fourier_mp.h"
+
+namespace fwr {
+namespace fs {
+
+using namespace mp;
+
+constexpr int RB = NN / R;  // row blocks of 16 rows
+
+enum : int {
+  kInit = 0,        // measurement (zeros outside the pupil) -> forward rows -> spec
+  kInitStore = 1,   // measurement -> state, Eq. 5 sums (no iteration)
+  kStep = 2,        // spec -> inverse rows -> step 4 -> forward rows -> spec
+  kStepStore = 3,   // spec -> inverse rows -> step 4 -> state, Eq. 5 sums
+  kFixFwd = 4,      // state -> Eq. 5 (with `fix`) -> forward rows -> spec
+  kFixExt = 5,      // state -> Eq. 5 (with `fix`) -> extended slopes [2][N][N]
+  kOut = 6          // spec -> inverse rows -> (n+1) x (n+1) phase window (real part)
+};
+
+__device__ __forceinline__ size_t fld(int f) { return (size_t)f * NN * NN; }
+
+// measured s_x + i s_y of cell (m, c) of frame f, 0 outside the pupil
+__device__ __forceinline__ float2 meas(const FSArgs &a, int f, int m, int c) {
+  const unsigned i = unsigned(m - a.o), j = unsigned(c - a.o);
+  const bool in = i < unsigned(a.n) && j < unsigned(a.n) && a.mask[i * a.n + j] != 0;
+  const size_t plane = (size_t)a.n * a.n, idx = in ? (size_t)i * a.n + j : 0;
+  const float *s = a.slopes + (size_t)f * 2 * plane;
+  const float x = s[idx], y = s[plane + idx];  // (cell 0 when outside: a valid read)
+  return in ? make_float2(x, y) : make_float2(0.f, 0.f);
+}
+
+__device__ __forceinline__ bool in_pupil(const FSArgs &a, int m, int c) {
+  const unsigned i = unsigned(m - a.o), j = unsigned(c - a.o);
+  return i < unsigned(a.n) && j < unsigned(a.n) && a.mask[i * a.n + j] != 0;
+}
+
+// rows m0 .. m0 + 15 of frame blockIdx.y, row block blockIdx.x + b0
+__global__ __launch_bounds__(THREADS) void rows_kernel(FSArgs a, int mode, int b0, int fix) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  __shared__ float red[R * R];
+  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
+  const int f = blockIdx.y, rb = blockIdx.x + b0, m0 = rb * R;
+  tw[t] = a.tw256[t];
+  constexpr int PASSES = R * NN / THREADS;  // one grid row per pass of the block
+  if (mode == kInit || mode == kInitStore) {
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) L[c_ * LP + pad(t)] = meas(a, f, m0 + c_, t);
+  } else if (mode == kFixFwd || mode == kFixExt) {
+    const float2 *S = a.state + fld(f);
+    float2 v[PASSES];
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) v[c_] = S[(size_t)(m0 + c_) * NN + t];
+    if (fix) {
+      // Eq. 5: s_x(m, N-1) -= R_m, s_y(N-1, c) -= C_c (C_c summed over the row blocks in order)
+      if (t == NN - 1) {
+#pragma unroll
+        for (int c_ = 0; c_ < PASSES; ++c_) v[c_].x -= a.rsum[(size_t)f * NN + m0 + c_];
+      }
+      if (rb == RB - 1) {
+        float cs = 0.f;
+        for (int b = 0; b < RB; ++b) cs += a.cpart[((size_t)f * RB + b) * NN + t];
+        v[PASSES - 1].y -= cs;
+      }
+    }
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) L[c_ * LP + pad(t)] = v[c_];
+  } else {
+    const float2 *S = a.spec + fld(f);
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) L[c_ * LP + pad(t)] = S[(size_t)(m0 + c_) * NN + t];
+  }
+  __syncthreads();
+  if (mode == kStep || mode == kStepStore || mode == kOut) {
+    fft_stage_b<+1>(L + rl * LP, r);
+    __syncthreads();
+    fft_stage_a<+1>(L + rl * LP, r, tw);
+    __syncthreads();
+  }
+  if (mode == kOut) {
+    const int n1 = a.n + 1;
+    float *o = a.out + (size_t)f * n1 * n1;
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) {
+      const int m = m0 + c_;
+      if (m >= a.o && m <= a.o + a.n && t >= a.o && t <= a.o + a.n)
+        o[(size_t)(m - a.o) * n1 + (t - a.o)] = L[c_ * LP + pad(t)].x;
+    }
+    return;
+  }
+  if (mode == kStep || mode == kStepStore) {
+    // step 4: the measurement inside the pupil, the extrapolation outside
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) {
+      const int m = m0 + c_;
+      if (in_pupil(a, m, t)) L[c_ * LP + pad(t)] = meas(a, f, m, t);
+    }
+    __syncthreads();
+  }
+  if (mode == kFixExt) {
+    const size_t gplane = (size_t)NN * NN;
+    float *e = a.out + (size_t)f * 2 * gplane;
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) {
+      const float2 v = L[c_ * LP + pad(t)];
+      e[(size_t)(m0 + c_) * NN + t] = v.x;
+      e[gplane + (size_t)(m0 + c_) * NN + t] = v.y;
+    }
+    return;
+  }
+  if (mode == kInitStore || mode == kStepStore) {
+    float2 *S = a.state + fld(f);
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) S[(size_t)(m0 + c_) * NN + t] = L[c_ * LP + pad(t)];
+    // Eq. 5 sums in a fixed order: R_m over the row (16 partials of 16), C partials over the block
+    float part = 0.f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) part += L[rl * LP + pad(r + R * q)].x;
+    red[rl * R + r] = part;
+    float cs = 0.f;
+#pragma unroll
+    for (int c_ = 0; c_ < PASSES; ++c_) cs += L[c_ * LP + pad(t)].y;
+    a.cpart[((size_t)f * RB + rb) * NN + t] = cs;
+    __syncthreads();
+    if (r == 0) {
+      float rs = 0.f;
+      for (int q = 0; q < R; ++q) rs += red[rl * R + q];
+      a.rsum[(size_t)f * NN + m0 + rl] = rs;
+    }
+    return;
+  }
+  // forward row FFTs -> spectrum
+  fft_stage_a<-1>(L + rl * LP, r, tw);
+  __syncthreads();
+  fft_stage_b<-1>(L + rl * LP, r);
+  __syncthreads();
+  float2 *S = a.spec + fld(f);
+#pragma unroll
+  for (int c_ = 0; c_ < PASSES; ++c_) S[(size_t)(m0 + c_) * NN + t] = L[c_ * LP + pad(t)];
+}
+
+// column position held by line c of column block g, and the line holding its mirror
+__device__ __forceinline__ int col_pos(int g, int c) {
+  if (g == 0) return c;
+  if (g == 1) return 8 * R + c;
+  const int a = 1 + (g - 2) / 2, h = (g - 2) & 1;
+  return c < 8 ? R * a + 8 * h + c : R * (R - a) + 8 * (1 - h) + (c - 8);
+}
+__device__ __forceinline__ int mirror_line(int g, int c) {
+  if (g == 0) return (R - c) & (R - 1);
+  return R - 1 - c;  // group 8: 128 + c <-> 128 + 15 - c; paired groups: line c <-> line 15 - c
+}
+// position of the mirrored frequency along a transformed line
+__device__ __forceinline__ int mirror_pos(int p) {
+  const int a = p >> 4, b = p & (R - 1);
+  return a == 0 ? (R - b) & (R - 1) : R * (R - a) + (R - 1) - b;
+}
+
+__global__ __launch_bounds__(THREADS) void cols_kernel(FSArgs a, int fin) {
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x, cl = t >> 4, r = t & 15;
+  const int f = blockIdx.y, g = blockIdx.x;
+  tw[t] = a.tw256[t];
+  float2 *S = a.spec + fld(f);
+  constexpr int NL = R * NN / THREADS;
+  {
+    const int c = t & (R - 1), row0 = t >> 4, p = col_pos(g, c);
+    float2 v[NL];
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) v[c_] = S[(size_t)(row0 + R * c_) * NN + p];
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) L[c * LP + pad(row0 + R * c_)] = v[c_];
+  }
+  __syncthreads();
+  fft_stage_a<-1>(L + cl * LP, r, tw);
+  __syncthreads();
+  fft_stage_b<-1>(L + cl * LP, r);
+  __syncthreads();
+  // Z' = alpha Z + beta conj(Zm) (loop) or A Z + B conj(Zm) (final), Zm = Z(-l, -k)
+  const int pc = col_pos(g, cl), ml = mirror_line(g, cl);
+  float2 out[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int q = r + R * j;
+    const float2 z = L[cl * LP + pad(q)];
+    const float2 zm = L[ml * LP + pad(mirror_pos(q))];
+    const size_t ti = (size_t)pc * NN + q;
+    if (fin) {
+      const float2 A = a.fin_a[ti], Bc = a.fin_b[ti];
+      out[j] = make_float2(A.x * z.x - A.y * z.y + Bc.x * zm.x + Bc.y * zm.y,
+                           A.x * z.y + A.y * z.x + Bc.y * zm.x - Bc.x * zm.y);
+    } else {
+      const float al = a.alpha[ti];
+      const float2 be = a.beta[ti];
+      out[j] = make_float2(al * z.x + be.x * zm.x + be.y * zm.y, al * z.y + be.y * zm.x - be.x * zm.y);
+    }
+  }
+  __syncthreads();  // every mirror read is done before the lines are overwritten
+#pragma unroll
+  for (int j = 0; j < R; ++j) L[cl * LP + pad(r + R * j)] = out[j];
+  __syncthreads();
+  fft_stage_b<+1>(L + cl * LP, r);
+  __syncthreads();
+  fft_stage_a<+1>(L + cl * LP, r, tw);
+  __syncthreads();
+  {
+    const int c = t & (R - 1), row0 = t >> 4, p = col_pos(g, c);
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) S[(size_t)(row0 + R * c_) * NN + p] = L[c * LP + pad(row0 + R * c_)];
+  }
+}
+
+}  // namespace fs
+
+bool fourier_mp_supported(int N) { return N == mp::NN; }
+
+size_t fourier_mp_workspace_bytes(int N, int max_batch) {
+  if (N != mp::NN) return 0;
+  const size_t B = (size_t)max_batch, NNs = (size_t)N * N;
+  return B * (2 * NNs * sizeof(float2) + (size_t)N * sizeof(float) + (size_t)(N / 16) * N * sizeof(float));
+}
+
+hipError_t fourier_mp_run(const FSArgs &a, bool extend, hipStream_t s) {
+  using namespace fs;
+  const dim3 grid(RB, a.B), blk(THREADS);
+  const bool each = (a.flags & kFourierPeriodicEach) != 0;
+  const int fix = ((a.flags & kFourierPeriodic) != 0 || (each && a.n_iter > 0)) ? 1 : 0;
+  if (a.n_iter == 0) {
+    hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kInitStore), 0, 0);
+  } else {
+    hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kInit), 0, 0);
+    for (int it = 0; it < a.n_iter; ++it) {
+      const bool last = it == a.n_iter - 1;
+      hipLaunchKernelGGL(cols_kernel, grid, blk, 0, s, a, 0);
+      if (!last && !each) {
+        hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kStep), 0, 0);
+        continue;
+      }
+      hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kStepStore), 0, 0);
+      if (!last) hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kFixFwd), 0, 1);  // per-iteration Eq. 5
+    }
+  }
+  if (extend) {
+    hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kFixExt), 0, fix);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kFixFwd), 0, fix);
+  hipLaunchKernelGGL(cols_kernel, grid, blk, 0, s, a, 1);
+  // the output is the window rows o .. o + n
+  const int w0 = a.o / mp::R, w1 = (a.o + a.n) / mp::R;
+  hipLaunchKernelGGL(rows_kernel, dim3(w1 - w0 + 1, a.B), blk, 0, s, a, int(kOut), w0, 0);
+  return hipGetLastError();
+}
+
+}  // namespace fwr

@@ -121,8 +121,15 @@ def test_sinc_unsupported_calls(F):
     x = torch.zeros((2, 2, 40, 40), device="cuda")
     with pytest.raises(F.FwrError):
         plan.generate(2, 1)
-    with pytest.raises(F.FwrError):
-        F.Plan(128, 256, I.pupil_mask(128), max_batch=1, model="sinc")
+    big = F.Plan(128, 256, I.pupil_mask(128), n_iter=2, max_batch=2, model="sinc")   # multi-pass grid
+    xb = torch.zeros((2, 2, 128, 128), device="cuda")
+    with pytest.raises(F.FwrError) as e:
+        big.reconstruct(xb, start=torch.zeros((2, 2, 256, 256), device="cuda"))
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+    with pytest.raises(F.FwrError) as e:
+        big.hudgin_extend(xb)
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+    big.close()
     plan.close()
 
 
@@ -234,3 +241,59 @@ def test_sinc_128_start_values_and_residual(F):
         assert _rel(got[b], O.reconstruct(s64, mask, p, start=st)) <= 1e-5
         assert abs(r[b] - O.extend(s64, mask, p, start=st).residuals[-1]) <= 1e-4 * r[b]
     plan.close()
+
+
+@pytest.mark.parametrize("n,n_iter,periodic,each,dpx", [(128, 20, True, False, 0.0), (128, 5, False, False, 0.0),
+                                                       (128, 3, True, True, 0.0), (128, 0, True, False, 0.0),
+                                                       (128, 6, True, False, 1.0 / 6.0), (254, 4, True, False, 0.0)])
+def test_sinc_256_multipass_matches_oracle(F, n, n_iter, periodic, each, dpx):
+    """The lenslet-averaging model on the 256 x 256 grid (multi-pass through HBM): phase and
+    extended slopes against the oracle (measured slopes bit for bit), ELT frames measured with the
+    model (D = 39 m), with and without Eq. 5, per-iteration Eq. 5, zero iterations, the d - d_px
+    correction, and a one-cell border (n = 254)."""
+    import dataclasses
+    _flush(f"[gpu] sinc 256 n={n} it={n_iter} periodic={periodic} each={each} dpx={dpx:.3f}")
+    N, B = 256, 3
+    if n == 128:
+        w = dataclasses.replace(I.ELT_128, model="sinc", d_px_frac=dpx, config_id=7)
+        slopes = I.make_batch(w, B, dtype=np.float32)
+        mask = I.pupil_mask(n)
+    else:
+        mask = I.random_mask(n, seed=5)
+        slopes = I.random_slopes(B, n, seed=6).astype(np.float32)
+    d = 39.0 / n
+    p = O.Params(n_sub=n, n_grid=N, n_iter=n_iter, periodic=periodic, periodic_each_iter=each, d=d,
+                 d_px=dpx * d, model="sinc")
+    plan = _plan(F, p, mask, B)
+    x = torch.from_numpy(slopes).cuda()
+    got = plan.reconstruct(x).cpu().numpy().astype(np.float64)
+    ext = plan.extend(x).cpu().numpy().astype(np.float64) if n_iter > 0 else None
+    o = (N - n) // 2
+    m = mask.astype(bool)
+    for b in range(B):
+        s64 = slopes[b].astype(np.float64)
+        assert _rel(got[b], O.reconstruct(s64, mask, p)) <= 1e-5, (b, _rel(got[b], O.reconstruct(s64, mask, p)))
+        if ext is not None:
+            ref = O.extend(s64, mask, p)
+            scale = np.sqrt(np.mean(ref.sx ** 2 + ref.sy ** 2))
+            assert np.abs(ext[b, 0] - ref.sx).max() <= 1e-4 * scale
+            assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
+            assert np.array_equal(ext[b, 0, o:o + n, o:o + n][m], slopes[b, 0][m].astype(np.float64))
+            assert np.array_equal(ext[b, 1, o:o + n, o:o + n][m], slopes[b, 1][m].astype(np.float64))
+    plan.close()
+
+
+def test_sinc_256_in_a_grouped_call(F):
+    """A multi-pass sinc plan beside an on-chip sinc plan and a Fried plan in one grouped call gives
+    the bits of the individual calls."""
+    _flush("[gpu] grouped call with the sinc multi-pass path")
+    items = []
+    for n, N, model in ((128, 256, "sinc"), (40, 80, "sinc"), (128, 256, "fried")):
+        plan = F.Plan(n, N, I.pupil_mask(n), n_iter=3, periodic=True, max_batch=2, d=8.0 / n, model=model)
+        x = torch.from_numpy(I.random_slopes(2, n, seed=n + N).astype(np.float32)).cuda()
+        items.append((plan, x, torch.empty((2, n + 1, n + 1), device="cuda"), None, None))
+    F.reconstruct_group(items)
+    torch.cuda.synchronize()
+    for plan, x, o, _, _ in items:
+        assert torch.equal(o, plan.reconstruct(x)), (plan.n_sub, plan.model)
+        plan.close()
