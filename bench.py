@@ -144,11 +144,17 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes for input generation (0 = up to 16; use 1 under a profiler)")
-    ap.add_argument("--workload", choices=("sphere40", "elt128", "uneven", "sinc40"), default="sphere40",
+    ap.add_argument("--workload", choices=("sphere40", "elt128", "uneven", "sinc40", "single", "learned40"),
+                    default="sphere40",
                     help="sphere40: the headline 4096 x 40x40 batch; elt128: 128 x 128x128 frames on "
                          "the 256x256 multi-pass path; uneven: the mixed-size closed loop captured in a "
-                         "HIP graph; sinc40: the headline batch with the lenslet-averaging slope model "
-                         "(each prints its own line)")
+                         "HIP graph; sinc40: the headline batch with the lenslet-averaging slope model; "
+                         "single: one grid size alone (--n-sub, --frames, --iters, --model); learned40: "
+                         "the learned start on the headline batch (each prints its own line)")
+    ap.add_argument("--n-sub", type=int, default=24, help="single workload: lenslets per side (grid 2n)")
+    ap.add_argument("--frames", type=int, default=2048, help="single workload: frames per launch")
+    ap.add_argument("--iters", type=int, default=N_ITER, help="single / learned40 workload: loop iterations")
+    ap.add_argument("--model", choices=("fried", "sinc"), default="fried", help="single workload: slope model")
     ap.add_argument("--graph-steps", type=int, default=1000,
                     help="uneven workload: timed graph replays (one loop step each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -169,6 +175,10 @@ def main():
         return uneven_main(args)
     if args.workload == "sinc40":
         return sinc_main(args)
+    if args.workload == "single":
+        return single_main(args)
+    if args.workload == "learned40":
+        return learned_main(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (frames are independent; see the design notes "
               f"for how the batch shards): --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -316,14 +326,21 @@ def sinc_main(args):
     import torch
     from paper_1705_04298_amd import fwr
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    if args.gen_workers:
+        workers = args.gen_workers
     jobs = [(s0, min(64, args.batch - s0)) for s0 in range(0, args.batch, 64)]
-    with mp.get_context("fork").Pool(workers) as pool:
-        slopes = np.concatenate(pool.map(_gen_sinc, jobs), axis=0)
     sample = min(args.cpu_sample, args.batch)
-    _CPU_SLOPES = slopes
-    parts = [np.arange(sample)[w::workers] for w in range(workers)]
-    with mp.get_context("fork").Pool(workers) as pool:
-        ref = {i: ph for part in pool.map(_oracle_sinc, parts) for i, ph in part}
+    if workers == 1:  # no worker processes (under a profiler)
+        slopes = np.concatenate([_gen_sinc(j) for j in jobs], axis=0)
+        _CPU_SLOPES = slopes
+        ref = dict(_oracle_sinc(np.arange(sample)))
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            slopes = np.concatenate(pool.map(_gen_sinc, jobs), axis=0)
+        _CPU_SLOPES = slopes
+        parts = [np.arange(sample)[w::workers] for w in range(workers)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            ref = {i: ph for part in pool.map(_oracle_sinc, parts) for i, ph in part}
     torch.cuda.set_device(0)
     plan = fwr.Plan(N_SUB, N_GRID, I.pupil_mask(N_SUB), n_iter=N_ITER, periodic=True, max_batch=args.batch,
                     model="sinc")
@@ -359,6 +376,139 @@ def sinc_main(args):
                                       "median_rel_rms": float(np.median(errs)), "tolerance": 1e-5},
         "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / FP32_VECTOR_PEAK, "traffic": None},
+    }), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    """Mean ms per call of `fn` between HIP events on the current stream, after `warmup` calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def single_main(args):
+    """One grid size alone: `--frames` frames of `--n-sub` x `--n-sub` lenslets padded to 2n,
+    `--iters` iterations + Eq. 5 + MMSE, slopes resident in HBM.  Fried frames come from the device
+    generator (D = 8 m, or 39 m for n = 128), lenslet-averaging frames from the host generator.
+    On-chip grids: FP32 roofline of the algorithmic FFT work; the 256 x 256 grid: HBM roofline of
+    2 MiB per frame and iteration (two round trips of a 512 KiB complex field)."""
+    import dataclasses
+    import torch
+    from paper_1705_04298_amd import fwr
+    n, B, it = args.n_sub, args.frames, args.iters
+    N = 2 * n
+    D = 39.0 if n == 128 else 8.0
+    torch.cuda.set_device(0)
+    plan = fwr.Plan(n, N, I.pupil_mask(n), n_iter=it, periodic=True, gamma=1.0, noise_var=0.05 ** 2,
+                    r0=0.15, L0=25.0, d=D / n, max_batch=B, model=args.model)
+    if args.model == "fried":
+        x, _ = plan.generate(B, 0x5EED_0517, r0=0.15, L0=25.0, sigma=0.05)
+    else:
+        w = dataclasses.replace(I.SPHERE_40_SINC, n_sub=n, diameter=D, screen_size=512 if N > 128 else 256,
+                                config_id=8)
+        x = torch.from_numpy(I.make_batch(w, B, dtype=np.float32)).cuda()
+    if not args.no_autotune:
+        plan.autotune(B)
+    threads, fpg, lds = plan.launch_info()
+    sched = plan.schedule
+    out = torch.empty((B, n + 1, n + 1), device="cuda")
+    ms = _timed(lambda: plan.reconstruct(x, out), args.steps, args.warmup)
+    if N <= 128:
+        flops = algorithmic_flops_per_frame(N, it) * B
+        roof = {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / FP32_VECTOR_PEAK, "traffic": None}
+    else:
+        alg = B * (it * 2 * 2 ** 20 + 2 * n * n * 4 + (n + 1) ** 2 * 4)
+        roof = {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": alg / (ms / 1e3) / 8e12, "traffic": None}
+    plan.close()
+    print(json.dumps({"metric": f"frames/s ({n}x{n} SH, {N}x{N} grid, {it} Gerchberg iters, {args.model} model)",
+                      "value": B / (ms / 1e3), "unit": "frames/s", "ms_per_step": ms, "steps": args.steps,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"{B} frames {n}x{n} -> {N}x{N}, {it} iterations + Eq.5 + MMSE",
+                                 "threads_per_group": threads, "frames_per_group": fpg,
+                                 "lds_bytes_per_group": lds, "fft_radix_schedule": sched},
+                      "roofline": roof}), flush=True)
+
+
+def cnn_forward_bytes_per_frame(N: int) -> int:
+    """Algorithmic HBM bytes of one network forward per N x N frame: the slopes in, the features
+    (8 BF16 channels), each layer's BF16 input and output activations read / written once (32
+    channels; the last layer writes 2 FP32 channels)."""
+    px = N * N
+    feats = 2 * N_SUB * N_SUB * 4 + px * 8 * 2
+    layers = px * (8 * 2 + 32 * 2) + 5 * px * (32 * 2 + 32 * 2) + px * (32 * 2 + 2 * 4)
+    return feats + layers
+
+
+def learned_main(args):
+    """The learned start on the headline batch (4096 x 40x40 -> 80x80): the network forward alone
+    (roofline: HBM, each activation read and written once per layer), the network + `--iters`
+    iterations, the plain 10-iteration loop, and the one-call learned reconstruction with the plain
+    loop as fallback (threshold twice the plain-10 median residual)."""
+    import torch
+    from paper_1705_04298_amd import fwr
+    from paper_1705_04298_amd import learned as L
+    B = args.batch
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    if args.gen_workers == 1:  # no worker processes (under a profiler)
+        slopes = I.make_batch(I.SPHERE_40_BATCH, B, dtype=np.float32)
+    else:
+        slopes = make_inputs(B, args.gen_workers or workers)
+    torch.cuda.set_device(0)
+    mask = I.pupil_mask(N_SUB)
+    x = torch.from_numpy(slopes).cuda()
+    params = np.load(os.path.join(ROOT, "paper_1705_04298_amd", "weights", "cnn_40x40_fried.npz"))["params"]
+    net = fwr.CNN(N_SUB, N_GRID, mask, max_batch=B, input_scale=L.INPUT_SCALE)
+    net.set_params(params)
+    start = torch.empty((B, 2, N_GRID, N_GRID), device="cuda")
+    kw = dict(periodic=True, gamma=1.0, noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=0.2, max_batch=B)
+    plan_k = fwr.Plan(N_SUB, N_GRID, mask, n_iter=args.iters, **kw)
+    plain = fwr.Plan(N_SUB, N_GRID, mask, n_iter=N_ITER, **kw)
+    out = torch.empty((B, N_SUB + 1, N_SUB + 1), device="cuda")
+    resid = torch.empty(B, device="cuda")
+    ms_net = _timed(lambda: net.forward(x, start), args.steps, args.warmup)
+    ms_k = _timed(lambda: (net.forward(x, start), plan_k.reconstruct(x, out, start=start, resid=resid)),
+                  args.steps, args.warmup)
+    r_k = float(torch.median(resid))
+    ms_plain = _timed(lambda: plain.reconstruct(x, out, resid=resid), args.steps, args.warmup)
+    r_plain = float(torch.median(resid))
+    thr = 2.0 * r_plain
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def one_call():
+        st = fwr.fwr_reconstruct_learned_noalloc(plan_k.handle, plain.handle, net._h, x.data_ptr(), start.data_ptr(),
+                                                 out.data_ptr(), resid.data_ptr(), thr, B, count.data_ptr())
+        if st != fwr.FWR_OK:
+            raise fwr.FwrError(st, "fwr_reconstruct_learned_noalloc")
+    ms_call = _timed(one_call, args.steps, args.warmup)
+    nfall = int(count.item())
+    flop = B * 2.0 * N_GRID * N_GRID * sum(9 * ci * co for ci, co in L.LAYERS)
+    nbytes = B * cnn_forward_bytes_per_frame(N_GRID)
+    for h in (net, plan_k, plain):
+        h.close()
+    print(json.dumps({
+        "metric": f"frames/s, learned start + {args.iters} Gerchberg iters (40x40 SH, 80x80 grid)",
+        "value": B / (ms_k / 1e3), "unit": "frames/s", "ms_per_step": ms_k, "steps": args.steps,
+        "dtype": "bf16 network (FP32 accumulate) + f32 loop", "data": "synthetic",
+        "config": {"workload": f"{B} frames 40x40 -> 80x80, CNN start + {args.iters} iterations + Eq.5 + MMSE",
+                   "iters": args.iters},
+        "median_residual": {"cnn_plus_k": r_k, "plain_10": r_plain},
+        "ms": {"network": ms_net, "network_plus_k": ms_k, "plain_10": ms_plain,
+               "one_call_with_fallback": ms_call},
+        "fallback": {"threshold": thr, "frames_recomputed": nfall, "frames": B},
+        "network_mfma_tflops": flop / (ms_net / 1e3) / 1e12,
+        "roofline": {"bound": "hbm", "achieved": nbytes / (ms_net / 1e3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": nbytes / (ms_net / 1e3) / 8e12, "traffic": None,
+                     "bytes_per_frame": cnn_forward_bytes_per_frame(N_GRID)},
     }), flush=True)
 
 
