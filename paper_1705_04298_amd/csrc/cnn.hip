@@ -48,29 +48,33 @@ constexpr int kpad() { return ((9 * CIN + 31) / 32) * 32; }
 #ifndef FWR_CNN_TILE_ROWS
 #define FWR_CNN_TILE_ROWS 4
 #endif
-constexpr int kTileRows = FWR_CNN_TILE_ROWS;  // output rows per workgroup of the convolution
+constexpr int kTileRows = FWR_CNN_TILE_ROWS;  // output rows per step of the convolution
+constexpr int kSegTiles = 5;  // consecutive row tiles of one frame per work item
 
 // ------------------------------------------------------------------ forward / backward-data
-// One workgroup = kTileRows output rows of one frame.  The (kTileRows + 2) x (N + 2) input
-// halo (zeros outside the frame) is staged once in LDS, so every input pixel is fetched from
-// memory once per tile instead of once per tap; pixel vectors are padded by 8 bf16 so that
-// the 16 pixels of an A operand fall on different LDS banks.  The weights (B operands) stay
-// in registers; each wave takes every 4th 16-pixel M tile of the workgroup.
+// A work item is a segment of kSegTiles row tiles (kTileRows output rows each) of one frame,
+// walked top to bottom.  The (kTileRows + 2) x (N + 2) input halo (zeros outside the frame)
+// lives in LDS as a ring of kTileRows + 2 rows: grid row y sits in ring row (y + 1) mod
+// (kTileRows + 2), so a tile keeps the two rows it shares with the previous one and loads only
+// kTileRows new rows; an input row is fetched from memory once per segment (plus the two halo
+// rows at its start) instead of once per tap or once per tile.  Pixel vectors are padded by
+// 8 bf16 so that the 16 pixels of an A operand fall on different LDS banks.  The weights
+// (B operands) stay in registers; each wave takes every 4th 16-pixel M tile of the tile.
 // MODE 0: y = relu(conv + bias) -> bf16 NHWC [.., 32]
 // MODE 1: y = (conv + bias) * out_scale for channels 0, 1 -> fp32 planar [B][2][N][N]
 // MODE 2: y = conv * (act[p][c] > 0) -> bf16 NHWC [.., COUT] (gradient through the ReLU)
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ x, const uint16_t *__restrict__ wt,
                                                    const float *__restrict__ bias, void *out,
-                                                   const uint16_t *__restrict__ act, int N, int ntiles,
+                                                   const uint16_t *__restrict__ act, int N, int nitems,
                                                    float out_scale) {
   // C^T = W^T X^T per 16-pixel tile: A = weights (16 output channels x 32 k), B = activations
   // (32 k x 16 pixels), so lane l ends with channels 4 (l / 16) .. + 3 of pixel l % 16.
-  // Persistent: the weights are loaded once; the workgroup walks the row tiles
+  // Persistent: the weights are loaded once; the workgroup walks the work items
   // blockIdx.x, blockIdx.x + gridDim.x, ...
   constexpr int K = kpad<CIN>(), KCH = K / 32, MT = COUT / 16, CP = CIN + 8, CH = CIN / 8;
   constexpr int PIX_STEP = 256 / CH;  // halo pixels staged per pass of the workgroup
-  extern __shared__ __attribute__((aligned(16))) uint16_t halo[];  // [kTileRows + 2][N + 2][CP]
+  extern __shared__ __attribute__((aligned(16))) uint16_t halo[];  // ring [kTileRows + 2][N + 2][CP]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
   bf16x8 aw[KCH][MT];
@@ -83,20 +87,29 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int i = 0; i < 4; ++i) bv[mt][i] = MODE == 2 ? 0.f : bias[mt * 16 + 4 * kq + i];
-  const int tiles = (N + kTileRows - 1) / kTileRows;
-  const int W = N + 2, hpix = (kTileRows + 2) * W;
+  const int tiles = (N + kTileRows - 1) / kTileRows, segs = (tiles + kSegTiles - 1) / kSegTiles;
+  constexpr int RING = kTileRows + 2;
+  const int W = N + 2, hpix = RING * W;
   const size_t NN = (size_t)N * N;
   const int c8 = threadIdx.x % CH;
 #pragma unroll 1
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int f = tile / tiles;
-    const int y0 = (tile - f * tiles) * kTileRows;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int f = item / segs, seg = item - f * segs;
+  const int kt0 = seg * kSegTiles, kt1 = kt0 + kSegTiles < tiles ? kt0 + kSegTiles : tiles;
+  const uint16_t *xf = x + (size_t)f * NN * CIN;
+#pragma unroll 1
+  for (int tile_k = kt0; tile_k < kt1; ++tile_k) {
+    const int y0 = tile_k * kTileRows;
     const int rows = N - y0 < kTileRows ? N - y0 : kTileRows;
-    const uint16_t *xf = x + (size_t)f * NN * CIN;
+    const int base = y0 % RING;  // ring row of halo row 0 (grid row y0 - 1)
+    auto ring = [&](int j) { return base + j >= RING ? base + j - RING : base + j; };
     __syncthreads();  // the previous tile's LDS reads are done
-    // halo pixel q = (r, xx + 1): walk q = threadIdx.x / CH + PIX_STEP * u, loads first, then stores
+    // halo rows j (grid row y0 - 1 + j) from jlo on: all of them at the segment's first tile, the
+    // kTileRows new ones after it.  Pixel q = (j, xx + 1): walk q = jlo W + threadIdx.x / CH +
+    // PIX_STEP u, loads first, then the stores into ring row ring(j)
     {
-      int q = threadIdx.x / CH, r = 0, xc = q;
+      const int jlo = tile_k == kt0 ? 0 : 2;
+      int q = jlo * W + threadIdx.x / CH, r = jlo, xc = threadIdx.x / CH;
       while (xc >= W) {
         xc -= W;
         ++r;
@@ -108,7 +121,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
           const int yy = y0 + r - 1, xx = xc - 1;
-          qs[u] = q;
+          qs[u] = q < hpix ? ring(r) * W + xc : -1;
           v[u] = make_uint4(0u, 0u, 0u, 0u);
           if (q < hpix && yy >= 0 && yy < N && xx >= 0 && xx < N)
             v[u] = *reinterpret_cast<const uint4 *>(xf + ((size_t)yy * N + xx) * CIN + 8 * c8);
@@ -121,7 +134,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u)
-          if (qs[u] < hpix) *reinterpret_cast<uint4 *>(halo + (size_t)qs[u] * CP + 8 * c8) = v[u];
+          if (qs[u] >= 0) *reinterpret_cast<uint4 *>(halo + (size_t)qs[u] * CP + 8 * c8) = v[u];
       }
     }
     __syncthreads();
@@ -152,12 +165,15 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
       f32x4 acc[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // LDS offsets of the pixel's three input rows (ring rows of halo rows r, r + 1, r + 2)
+      const int ro0 = (ring(r) * W + xx) * CP, ro1 = (ring(r + 1) * W + xx) * CP, ro2 = (ring(r + 2) * W + xx) * CP;
 #pragma unroll
       for (int kc = 0; kc < KCH; ++kc) {
         const int k0 = kc * 32 + 8 * kq;
         const int t = k0 / CIN, c0 = k0 - t * CIN;
+        const int tr = t / 3, ro = tr == 0 ? ro0 : (tr == 1 ? ro1 : ro2);
         bf16x8 b = zero8();
-        if (t < 9) b = *reinterpret_cast<const bf16x8 *>(halo + ((size_t)(r + t / 3) * W + xx + t % 3) * CP + c0);
+        if (t < 9) b = *reinterpret_cast<const bf16x8 *>(halo + ro + (t % 3) * CP + c0);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[kc][mt], b, acc[mt], 0, 0, 0);
@@ -190,6 +206,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
         }
       }
     }
+  }
   }
 }
 
@@ -389,7 +406,11 @@ __global__ void pack_kernel(const float *__restrict__ w, uint16_t *__restrict__ 
 namespace cnn_launch {
 using namespace cnn;
 
-static int tiles_of(int B, int N) { return B * ((N + kTileRows - 1) / kTileRows); }
+// work items of a launch: kSegTiles-tile segments of every frame
+static int tiles_of(int B, int N) {
+  const int tiles = (N + kTileRows - 1) / kTileRows;
+  return B * ((tiles + kSegTiles - 1) / kSegTiles);
+}
 
 // persistent grid: as many workgroups as the CUs hold at once (occupancy of the kernel with
 // its dynamic LDS), capped by the number of tiles; measured once per kernel and grid size in
