@@ -40,11 +40,18 @@
  *     thrown across this boundary.  A kernel fault surfaces as FWR_E_DEVICE
  *     from a later call or from the caller's own stream synchronisation.
  *   - One plan may be used from one host thread at a time.
- *   - Non-finite input: the hot path does not test values.  Frames are
- *     transformed in pairs (frame 2i in the real part and 2i+1 in the
- *     imaginary part of one complex field), so a NaN or infinity in a
- *     frame's in-pupil slopes reaches the output of that frame and of its
- *     partner in the pair; other frames are unaffected.
+ *   - Non-finite input is isolated per frame.  Under the Fried model frames
+ *     are transformed in pairs (frame 2i in the real part and 2i+1 in the
+ *     imaginary part of one complex field); a NaN or infinity among a frame's
+ *     in-pupil measured slopes, or anywhere in its start values, enters that
+ *     field as zero and the frame is flagged: its phases, extended slopes and
+ *     residual are written as NaN (the residual then selects it for the
+ *     fallback).  Other pairs are untouched; the partner is bit for bit what
+ *     it is when the offending measured slopes are zero, and equal to rounding
+ *     when the offending values are start values.  Under the
+ *     lenslet-averaging model frames are not paired: such a frame's phases are
+ *     NaN and no other frame is touched.  Slopes outside the pupil are never
+ *     read.
  */
 #ifndef FWR_H
 #define FWR_H

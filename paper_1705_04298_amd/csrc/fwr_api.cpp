@@ -857,6 +857,7 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   a.sy = reinterpret_cast<float2 *>(w + 3 * pairs * fbytes);
   a.f0 = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes);
   a.sums = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes + pairs * (size_t)(n + 1) * N * sizeof(float2));
+  a.bad = reinterpret_cast<uint32_t *>(a.sums + pairs * 2 * (size_t)N);
   a.h_loop = reinterpret_cast<const float *>(mem);
   a.h_final = reinterpret_cast<const float *>(mem + off_hf);
   a.tw256 = reinterpret_cast<const float2 *>(mem + off_tw);

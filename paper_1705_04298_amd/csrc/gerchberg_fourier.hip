@@ -221,7 +221,7 @@ void fourier_kernel(FourierArgs a) {
           nt += sums[m].x;
           dt += sums[m].y;
         }
-        if (active) a.resid[f] = dt > 0.f ? sqrtf(nt / dt) : 0.f;
+        if (active) a.resid[f] = !(dt <= 0.f) ? sqrtf(nt / dt) : 0.f;  // (NaN stays NaN)
       }
       __syncthreads();  // the line sums are read before the buffer is used again
     }

@@ -50,14 +50,32 @@ __device__ __forceinline__ bool in_pupil(const uint8_t *mask, int n, int o, int 
   return i < unsigned(n) && j < unsigned(n) && mask[i * n + j] != 0;
 }
 
-// measured (s_x, s_y) of cell (cm, cn) for frames A (real) and B (imag)
-__device__ __forceinline__ void measured(const MPArgs &a, int pair, int cm, int cn, float2 &sx, float2 &sy) {
+// A frame's non-finite input must not reach its partner through the shared complex field:
+// every measured slope enters the field through clean() (non-finite values as zeros), and
+// the frame is flagged so that its output is written as NaN.
+__device__ __forceinline__ bool finite(float v) { return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u; }
+__device__ __forceinline__ float clean(float v) { return finite(v) ? v : 0.f; }
+__device__ __forceinline__ float nan_f() { return __uint_as_float(0x7fc00000u); }
+
+// measured (s_x, s_y) of cell (cm, cn) for frames A (real) and B (imag), cleaned; returns
+// the frames' non-finite bits (1: A, 2: B)
+__device__ __forceinline__ uint32_t measured(const MPArgs &a, int pair, int cm, int cn, float2 &sx, float2 &sy) {
   const int n = a.n, plane = n * n;
   const int idx = (cm - a.o) * n + (cn - a.o);
   const float *sa = a.slopes + (size_t)(2 * pair) * 2 * plane;
   const bool hasB = 2 * pair + 1 < a.B;
-  sx = make_float2(sa[idx], hasB ? sa[2 * plane + idx] : 0.f);
-  sy = make_float2(sa[plane + idx], hasB ? sa[3 * plane + idx] : 0.f);
+  const float ax = sa[idx], ay = sa[plane + idx];
+  const float bx = hasB ? sa[2 * plane + idx] : 0.f, by = hasB ? sa[3 * plane + idx] : 0.f;
+  sx = make_float2(clean(ax), clean(bx));
+  sy = make_float2(clean(ay), clean(by));
+  return (finite(ax) && finite(ay) ? 0u : 1u) | (finite(bx) && finite(by) ? 0u : 2u);
+}
+
+// non-finite bits of the pair, from the window row blocks' words
+__device__ __forceinline__ uint32_t pair_bad(const MPArgs &a, int pair) {
+  uint32_t bad = 0;
+  for (int b = 0; b <= (a.o + a.n) / R - a.o / R; ++b) bad |= a.bad[(size_t)pair * (NN / R) + b];
+  return bad;
 }
 
 // ---------------------------------------------------------------- row phase
@@ -78,8 +96,10 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   static_assert(R * LP <= (R + 2) * NN, "line buffer must fit in the phi rows");
   float2 *const L = ph;
   __shared__ float2 tw[NN];
+  __shared__ uint32_t badw;  // mode 0: the block's non-finite bits
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int mode = mode_arg == 2 && int(blockIdx.x) >= nw ? 3 : mode_arg;  // uniform per block
+  if (t == 0) badw = 0;
   const int pair = blockIdx.y, m0 = mode == 3 ? (int(blockIdx.x) == nw ? 0 : NN - R) : (blockIdx.x + b0) * R;
   const int m = m0 + rl;
   load_tw(tw, a.tw256, t);
@@ -108,6 +128,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   }
   __syncthreads();
   float2 fq[R];
+  uint32_t bad = 0;  // mode 0: every in-pupil cell is cell (m, nn) of one window-row node
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int nn = r + R * q;
@@ -116,7 +137,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
       if (win_row) {
         const int nl = (nn - 1) & (NN - 1), up = (m - 1) & (NN - 1);
         float2 sx, sy;
-        if (in_pupil(a.mask, a.n, a.o, m, nn)) { measured(a, pair, m, nn, sx, sy); f = csub(f, cadd(sx, sy)); }
+        if (in_pupil(a.mask, a.n, a.o, m, nn)) { bad |= measured(a, pair, m, nn, sx, sy); f = csub(f, cadd(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, up, nl)) { measured(a, pair, up, nl, sx, sy); f = cadd(f, cadd(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, m, nl)) { measured(a, pair, m, nl, sx, sy); f = cadd(f, csub(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
@@ -164,6 +185,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
       fq[q] = m == 0 ? make_float2(-cc.x, -cc.y) : (m == NN - 1 ? cc : make_float2(0.f, 0.f));
     }
   }
+  if (bad != 0) atomicOr(&badw, bad);
   __syncthreads();  // every stencil read of the phi rows is done
 #pragma unroll
   for (int q = 0; q < R; ++q) L[rl * LP + pad(r + R * q)] = fq[q];
@@ -172,6 +194,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   __syncthreads();
   fft_stage_b<-1>(L + rl * LP, r);
   __syncthreads();
+  if (mode == 0 && t == 0) a.bad[(size_t)pair * (NN / R) + blockIdx.x] = badw;  // (b0 = the first window block)
   float2 *S = a.spec + field(pair);
 #pragma unroll
   for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
@@ -214,8 +237,8 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
     const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
     const int idx = inw ? (m - o) * n + (nn - o) : 0;
     inp[q] = inw && a.mask[idx] != 0;
-    mx[q] = make_float2(sa[idx], hasB ? sb[idx] : 0.f);
-    my[q] = make_float2(sa[plane + idx], hasB ? sb[plane + idx] : 0.f);
+    mx[q] = make_float2(clean(sa[idx]), hasB ? clean(sb[idx]) : 0.f);
+    my[q] = make_float2(clean(sa[plane + idx]), hasB ? clean(sb[plane + idx]) : 0.f);
   }
   __syncthreads();
   float2 acc = make_float2(0.f, 0.f);
@@ -430,8 +453,8 @@ __global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero)
     const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
     const int idx = inw ? (m - o) * n + (nn - o) : 0;
     inp[q] = inw && a.mask[idx] != 0;
-    mx[q] = make_float2(sa[idx], sb[idx]);
-    my[q] = make_float2(sa[plane + idx], sb[plane + idx]);
+    mx[q] = make_float2(clean(sa[idx]), clean(sb[idx]));
+    my[q] = make_float2(clean(sa[plane + idx]), clean(sb[plane + idx]));
   }
   __syncthreads();
   float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
@@ -482,11 +505,12 @@ __global__ __launch_bounds__(THREADS) void ext_out_kernel(MPArgs a) {
   const bool hasB = 2 * pair + 1 < a.B;
   const size_t idx = (size_t)m * NN + t;
   const float2 x = SX[idx], y = SY[idx];
-  oa[idx] = x.x;
-  oa[plane + idx] = y.x;
+  const uint32_t bad = pair_bad(a, pair);
+  oa[idx] = bad & 1u ? nan_f() : x.x;
+  oa[plane + idx] = bad & 1u ? nan_f() : y.x;
   if (hasB) {
-    oa[2 * plane + idx] = x.y;
-    oa[3 * plane + idx] = y.y;
+    oa[2 * plane + idx] = bad & 2u ? nan_f() : x.y;
+    oa[3 * plane + idx] = bad & 2u ? nan_f() : y.y;
   }
 }
 
@@ -527,10 +551,11 @@ __global__ __launch_bounds__(THREADS) void phase_out_kernel(MPArgs a) {
   const float2 *P = a.phi + field(pair);
   float *oa = a.out + (size_t)(2 * pair) * n1 * n1;
   const bool hasB = 2 * pair + 1 < a.B;
+  const uint32_t bad = pair_bad(a, pair);
   for (int j = threadIdx.x; j < n1; j += THREADS) {
     const float2 v = P[(size_t)(a.o + i) * NN + a.o + j];
-    oa[(size_t)i * n1 + j] = v.x;
-    if (hasB) oa[(size_t)n1 * n1 + (size_t)i * n1 + j] = v.y;
+    oa[(size_t)i * n1 + j] = bad & 1u ? nan_f() : v.x;
+    if (hasB) oa[(size_t)n1 * n1 + (size_t)i * n1 + j] = bad & 2u ? nan_f() : v.y;
   }
 }
 
@@ -540,7 +565,8 @@ size_t multipass_workspace_bytes(int N, int n, int max_batch) {
   if (N != mp::NN) return 0;
   const size_t pairs = (size_t)(max_batch + 1) / 2;
   const size_t f = (size_t)N * N * sizeof(float2);
-  return pairs * (4 * f + (size_t)(n + 1) * N * sizeof(float2) + 2 * (size_t)N * sizeof(float2));
+  return pairs * (4 * f + (size_t)(n + 1) * N * sizeof(float2) + 2 * (size_t)N * sizeof(float2) +
+                 (size_t)(N / mp::R) * sizeof(uint32_t));
 }
 
 bool multipass_supported(int N) { return N == mp::NN; }

@@ -109,6 +109,18 @@ __device__ __forceinline__ float select_bits(bool c, float a, float b) {
   return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
 }
 
+// A frame's non-finite input must not reach its partner through the shared complex field:
+// measured and start slopes enter the field with non-finite values as zeros, and the frame
+// is flagged so that its outputs are written as NaN.
+__device__ __forceinline__ float nan_f() { return __uint_as_float(0x7fc00000u); }
+// The test is integer arithmetic (1: not finite; an all-ones exponent carries into bit 31),
+// and zero_if clears a non-finite value by masking its bits: no lane masks are held across
+// the batched loads.
+__device__ __forceinline__ uint32_t nonfinite_bit(float v) {
+  return ((__float_as_uint(v) & 0x7f800000u) + 0x00800000u) >> 31;
+}
+__device__ __forceinline__ float zero_if(float v, uint32_t nf) { return __uint_as_float(__float_as_uint(v) & (nf - 1u)); }
+
 // EACH: Eq. 5 after every iteration (flag kFlagPeriodicEach).
 // WIN: the pruned loop of the 2x-padded window (n = N/2, o = N/4) with the window fixed at
 // compile time, so that the zero lines and columns outside it fold away (launched only
@@ -128,6 +140,7 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   __shared__ float red_all[PAIRS * C::RED];
   __shared__ float2 tw[T * 4];
   __shared__ float2 twi[T * 4];  // inverse twiddles with the lane signs of the signed quad DFT
+  __shared__ uint32_t bad_all;   // non-finite input: bits 2 h (frame A) and 2 h + 1 (frame B) of pair h
   extern __shared__ float2 f0rows_all[];  // PAIRS x [(n+1)][PITCH], lane-blocked like the tile rows
 
   // this thread's frame pair within the workgroup and its LDS
@@ -171,6 +184,8 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   const int up = line == 0 ? N - 1 : line - 1;    // row m - 1
   const int dn = line == N - 1 ? 0 : line + 1;    // row m + 1
 
+  if (threadIdx.x == 0) bad_all = 0;  // (the atomics come after the first barrier)
+  uint32_t bad = 0;                   // this thread's non-finite bits (1: frame A, 2: frame B)
   for (int i = threadIdx.x; i < T * 4; i += Group<N, PAIRS>::THREADS) {
     const float2 w = a.tw_lane[i];
     const float sg = lane_sign(i & 3);
@@ -234,8 +249,10 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
 #pragma unroll
         for (int pl = 0; pl < 2; ++pl) {
           const float xa = sa[pl * plane + gi], xb = sbb[pl * plane + gi];
-          va[pl][c] = v ? xa : 0.f;
-          vb[pl][c] = v && hasB ? xb : 0.f;
+          const uint32_t na = nonfinite_bit(xa), nb2 = hasB ? nonfinite_bit(xb) : 0u;
+          bad |= v ? (na | (nb2 << 1)) : 0u;
+          va[pl][c] = v ? zero_if(xa, na) : 0.f;
+          vb[pl][c] = v && hasB ? zero_if(xb, nb2) : 0.f;
         }
       }
 #pragma unroll
@@ -273,7 +290,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
         const bool v = a.mask[i] != 0;
         const float va = sa[pass * plane + i];
         const float vb = sbb[pass * plane + i];
-        buf[i] = make_float2(v ? va : 0.f, v && hasB ? vb : 0.f);
+        const uint32_t na = nonfinite_bit(va), nb2 = hasB ? nonfinite_bit(vb) : 0u;
+        bad |= v ? (na | (nb2 << 1)) : 0u;
+        buf[i] = make_float2(v ? zero_if(va, na) : 0.f, v && hasB ? zero_if(vb, nb2) : 0.f);
       }
       __syncthreads();
       const float sgn3 = pass == 0 ? 1.f : -1.f;  // r = s_x - s_y
@@ -446,11 +465,15 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       if (kin_r(k)) buf[line * P + T * j + k] = x[k];
     }
     __syncthreads();
+    const uint32_t fb = write || want_resid ? bad_all >> (2 * half) : 0u;  // non-finite frames of the pair
+    const bool nan_a = (fb & 1u) != 0, nan_b = (fb & 2u) != 0;
     const unsigned wrow = unsigned(line >= o && line < o + n ? line - o : 0) * unsigned(n);
     const size_t gplane = (size_t)N * N;
     float *ea = a.out + (size_t)fa * 2 * gplane;  // extended slopes of frame A (write mode)
     float2 rowacc = make_float2(0.f, 0.f);  // minus the in-pupil model x slopes of the row
-    float ra = 0.f, rb = 0.f, na = 0.f, nb = 0.f;  // in-pupil misfit and measurement energy
+    // in-pupil misfit and measurement energy (a non-finite frame starts its energy at NaN, so
+    // that the reduction makes its residual NaN)
+    float ra = 0.f, rb = 0.f, na = nan_a ? nan_f() : 0.f, nb = nan_b ? nan_f() : 0.f;
     const bool need_meas = want_resid || write;
     float2 DY[EY_IN_F0 ? 1 : T];
     if (row_w) {  // (pruned: the other lines have no pupil cell and q2 = 0 there)
@@ -491,11 +514,11 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
           }
           if (write && active) {
             const size_t idx = (size_t)line * N + nn;
-            ea[idx] = select_bits(meas, mxa, gx.x);
-            ea[gplane + idx] = select_bits(meas, mya, gy.x);
+            ea[idx] = nan_a ? nan_f() : select_bits(meas, mxa, gx.x);
+            ea[gplane + idx] = nan_a ? nan_f() : select_bits(meas, mya, gy.x);
             if (hasB) {
-              ea[2 * gplane + idx] = select_bits(meas, mxb, gx.y);
-              ea[3 * gplane + idx] = select_bits(meas, myb, gy.y);
+              ea[2 * gplane + idx] = nan_b ? nan_f() : select_bits(meas, mxb, gx.y);
+              ea[3 * gplane + idx] = nan_b ? nan_f() : select_bits(meas, myb, gy.y);
             }
           }
         }
@@ -553,8 +576,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
           s2 += red[4 * w + 2];
           s3 += red[4 * w + 3];
         }
-        a.resid[fa] = s2 > 0.f ? sqrtf(s0 / s2) : 0.f;
-        if (hasB) a.resid[fa + 1] = s3 > 0.f ? sqrtf(s1 / s3) : 0.f;
+        // (a NaN energy passes the test: the residual of a non-finite frame is NaN)
+        a.resid[fa] = !(s2 <= 0.f) ? sqrtf(s0 / s2) : 0.f;
+        if (hasB) a.resid[fa + 1] = !(s3 <= 0.f) ? sqrtf(s1 / s3) : 0.f;
       }
     }
     if (fix) {
@@ -627,7 +651,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
 #pragma unroll
   for (int k = 0; k < T; ++k) x[k] = f0[k];  // q2 of the zero-padded start
   __syncthreads();                           // tables and forcing in LDS
-  if (a.start != nullptr) {
+  const bool has_start = !WIN && a.start != nullptr;  // (the WIN kernel is launched without start values)
+  if (bad != 0 && !has_start) atomicOr(&bad_all, bad << (2 * half));
+  if (has_start) {
     // q2 of the given start: add the adjoint stencil of the start slopes on the
     // out-of-pupil cells, -p(c1) + p(c2) + r(c3) - r(c4) (p = s_x + s_y, r = s_x - s_y),
     // staging p then r through the tile in the own-slot layout
@@ -635,12 +661,16 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
     const float *st = a.start + (size_t)fa * 2 * gplane;
     for (int pass = 0; pass < 2; ++pass) {
       const float sg = pass == 0 ? 1.f : -1.f;
-#pragma unroll
+#pragma unroll 4  // (staging only: a full unroll raises the register pressure of the whole kernel)
       for (int k = 0; k < T; ++k) {
         const size_t idx = (size_t)line * N + 4 * k + j;
         const float ax = st[idx], ay = st[gplane + idx];
         const float bx = hasB ? st[2 * gplane + idx] : 0.f, by = hasB ? st[3 * gplane + idx] : 0.f;
-        buf[line * P + T * j + k] = make_float2(fmaf(sg, ay, ax), fmaf(sg, by, bx));
+        // a non-finite start value makes p (or r) non-finite: that cell enters as zero
+        const float pa = fmaf(sg, ay, ax), pb = fmaf(sg, by, bx);
+        const uint32_t na = nonfinite_bit(pa), nb2 = nonfinite_bit(pb);
+        bad |= na | (nb2 << 1);
+        buf[line * P + T * j + k] = make_float2(zero_if(pa, na), zero_if(pb, nb2));
       }
       __syncthreads();
 #pragma unroll
@@ -662,7 +692,9 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
       }
       __syncthreads();
     }
+    if (bad != 0) atomicOr(&bad_all, bad << (2 * half));
   }
+  // (read after at least one more barrier: every solve and the final step begin with one)
 
   for (int it = 0; it < a.n_iter; ++it) {
     solve(x, a.h_loop, row_w, row_r1, WIN ? 1 : 0);
@@ -686,13 +718,15 @@ void gerchberg_onchip_kernel(OnchipArgs a) {
   if (active && line >= o && line <= o + n) {
     float *oa = a.out + (size_t)fa * (n + 1) * (n + 1);
     float *ob = oa + (size_t)(n + 1) * (n + 1);
+    const uint32_t fb = bad_all >> (2 * half);
+    const bool nan_a = (fb & 1u) != 0, nan_b = (fb & 2u) != 0;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       const int nn = 4 * k + j;
       if (nn >= o && nn <= o + n) {
         const size_t idx = (size_t)(line - o) * (n + 1) + (nn - o);
-        oa[idx] = x[k].x;
-        if (hasB) ob[idx] = x[k].y;
+        oa[idx] = nan_a ? nan_f() : x[k].x;
+        if (hasB) ob[idx] = nan_b ? nan_f() : x[k].y;
       }
     }
   }

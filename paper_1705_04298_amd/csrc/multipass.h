@@ -17,6 +17,8 @@ struct MPArgs {
   float2 *phi, *spec, *sx, *sy;
   float2 *f0;            // [pairs][n+1][N]
   float2 *sums;          // [pairs][2N]: C_n then R_m
+  uint32_t *bad;         // [pairs][N/16]: per window row block, bit 0 (frame A) and bit 1 (frame B)
+                         // set where an in-pupil measured slope is not finite
   const float *h_loop;   // [N][N], column position major, digit-reversed positions
   const float *h_final;
   const float2 *tw256;   // W_256^e, e = 0..255

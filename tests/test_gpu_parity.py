@@ -70,6 +70,7 @@ def check_reconstruct(F, slopes, mask, p, tag):
 
 
 SPHERE = dict(n_sub=40, n_grid=80, d=0.2, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
+ELT = dict(n_sub=128, n_grid=256, d=39.0 / 128, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
 
 
 def test_sphere40_periodic_10_iterations(fwr):
@@ -171,19 +172,51 @@ def test_bitwise_deterministic(fwr):
     assert np.array_equal(a, b)
 
 
-def test_frames_outside_a_pair_are_isolated(fwr):
-    """Frames are processed two per workgroup; a non-finite frame can only reach its partner."""
-    mask = I.pupil_mask(40)
-    slopes = I.make_batch(I.SPHERE_40, 6, start=70, dtype=np.float32)
-    p = O.Params(n_iter=4, periodic=True, **SPHERE)
-    clean = run_case(fwr, slopes, mask, p)
+def _isolation_case(case):
+    """(slopes, mask, params, what, bad cell) of one isolation case."""
+    if case.startswith("multipass"):
+        mask = I.pupil_mask(128)
+        slopes = I.make_batch(I.ELT_128, 5, start=40, dtype=np.float32)
+        p = O.Params(n_iter=3, periodic=True, **ELT)
+        cell = (64, 3)
+    else:
+        mask = I.pupil_mask(40)
+        slopes = I.make_batch(I.SPHERE_40, 5, start=70, dtype=np.float32)
+        p = O.Params(n_iter=4, periodic=True, periodic_each_iter=case == "each", **SPHERE)
+        cell = (20, 3)
+    assert mask[cell] == 1  # a valid subaperture (the centre is obstructed)
+    return slopes, mask, p, "extend" if case.endswith("extend") else "reconstruct", cell
+
+
+@pytest.mark.parametrize("case", ["win", "each", "extend", "multipass", "multipass_extend"])
+@pytest.mark.parametrize("which,value", [(2, np.nan), (3, np.inf), (4, -np.inf)])
+def test_non_finite_frame_is_isolated(fwr, case, which, value):
+    """Frames share a complex field in pairs (2i real, 2i+1 imaginary).  A frame with a
+    non-finite in-pupil slope gets an all-NaN output; every other frame, its partner included,
+    is bit for bit what it is when that slope is zero.  Frame 4 of the 5 has no partner."""
+    slopes, mask, p, what, cell = _isolation_case(case)
+    _flush(f"[gpu] isolation {case} frame={which} value={value}")
     bad = slopes.copy()
-    assert mask[20, 3] == 1       # a valid subaperture (the centre is obstructed)
-    bad[2, 0, 20, 3] = np.nan
-    dirty = run_case(fwr, bad, mask, p)
-    for b in (0, 1, 4, 5):
-        assert np.array_equal(clean[b], dirty[b])
-    assert np.isnan(dirty[2]).any()
+    bad[which, 1 if which == 3 else 0][cell] = value
+    ref = slopes.copy()
+    ref[which, 1 if which == 3 else 0][cell] = 0.0
+    got = run_case(fwr, bad, mask, p, what)
+    want = run_case(fwr, ref, mask, p, what)
+    assert np.isnan(got[which]).all()
+    others = [b for b in range(slopes.shape[0]) if b != which]
+    assert np.array_equal(got[others], want[others])
+    assert np.isfinite(got[others]).all()
+
+
+def test_non_finite_outside_the_pupil_is_ignored(fwr):
+    """Slopes of cells outside the pupil are not read: a NaN there changes nothing."""
+    mask = I.pupil_mask(40)
+    slopes = I.make_batch(I.SPHERE_40, 4, start=75, dtype=np.float32)
+    p = O.Params(n_iter=4, periodic=True, **SPHERE)
+    assert mask[0, 0] == 0
+    bad = slopes.copy()
+    bad[1, 0, 0, 0] = np.nan
+    assert np.array_equal(run_case(fwr, bad, mask, p), run_case(fwr, slopes, mask, p))
 
 
 def test_abi_errors(fwr):
@@ -260,7 +293,6 @@ def test_full_batch_sampled(fwr):
         assert rel_rms(got[b], want) <= REL_TOL, b
 
 
-ELT = dict(n_sub=128, n_grid=256, d=39.0 / 128, r0=0.15, L0=25.0, noise_var=0.05 ** 2)
 
 
 @pytest.mark.parametrize("n_iter,periodic,each", [(20, True, False), (0, True, False), (3, False, False),

@@ -114,3 +114,34 @@ def test_fallback_recomputes_frames_with_non_finite_residual(F):
     assert torch.equal(ph, plain.reconstruct(x))
     lr.close()
     plain.close()
+
+
+def test_non_finite_frame_in_learned_call_is_isolated(F):
+    """A NaN measured slope in frame 2: the network's start for that frame is non-finite around
+    the cell, the frame's phases and residual are NaN and it falls back to the plain loop (NaN
+    again).  Frames outside its pair are bit for bit those of the call with that slope zero;
+    its partner (frame 3) equals them to rounding (the two share complex transforms)."""
+    from paper_1705_04298_amd import learned as L
+    _flush("[gpu] learned call with a non-finite frame")
+    params = np.load(os.path.join(os.path.dirname(L.__file__), "weights", "cnn_40x40_fried.npz"))["params"]
+    B = 6
+    slopes, _ = L.make_frames(B, seed0=92_000)
+    cell = (20, 3)
+    assert I.pupil_mask(40)[cell] == 1
+    bad, ref = slopes.copy(), slopes.copy()
+    bad[2, 0][cell] = np.nan
+    ref[2, 0][cell] = 0.0
+    lr = L.LearnedReconstructor(params, n_iter=2, plain_iter=10, threshold=1e9, max_batch=B)
+    outs = []
+    for s in (bad, ref):
+        ph, resid, nfall = lr.reconstruct(torch.from_numpy(np.ascontiguousarray(s)).cuda())
+        torch.cuda.synchronize()
+        outs.append((ph.cpu().numpy().copy(), resid.cpu().numpy().copy(), nfall))
+    (pb, rb, nb), (pr, rr, nr) = outs
+    assert nr == 0 and nb == 1
+    assert np.isnan(pb[2]).all() and np.isnan(rb[2])
+    for b in (0, 1, 4, 5):
+        assert np.array_equal(pb[b], pr[b]) and rb[b] == rr[b]
+    e = np.sqrt(np.mean((pb[3] - pr[3]) ** 2) / np.mean(pr[3] ** 2))
+    assert e < 1e-5 and abs(rb[3] - rr[3]) <= 1e-4 * rr[3], (e, rb[3], rr[3])
+    lr.close()

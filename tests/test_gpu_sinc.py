@@ -297,3 +297,25 @@ def test_sinc_256_in_a_grouped_call(F):
     for plan, x, o, _, _ in items:
         assert torch.equal(o, plan.reconstruct(x)), (plan.n_sub, plan.model)
         plan.close()
+
+
+@pytest.mark.parametrize("n,N", [(40, 80), (128, 256)])
+def test_sinc_non_finite_frame_is_isolated(F, n, N):
+    """Frames are not paired under the lenslet-averaging model: a frame with a non-finite
+    in-pupil slope gets NaN phases and every other frame is unchanged, bit for bit."""
+    _flush(f"[gpu] sinc isolation n={n} N={N}")
+    mask = I.pupil_mask(n)
+    slopes = (I.make_batch(I.SPHERE_40_SINC, 3, start=40, dtype=np.float32) if n == 40
+              else np.random.default_rng(5).standard_normal((3, 2, n, n)).astype(np.float32))
+    p = O.Params(n_sub=n, n_grid=N, n_iter=3, periodic=True, d=8.0 / n, model="sinc")
+    cell = (n // 2, 3)
+    assert mask[cell] == 1
+    bad, ref = slopes.copy(), slopes.copy()
+    bad[1, 1][cell] = np.inf
+    ref[1, 1][cell] = 0.0
+    plan = _plan(F, p, mask, 3)
+    gb = plan.reconstruct(torch.from_numpy(bad).cuda()).cpu().numpy()
+    gr = plan.reconstruct(torch.from_numpy(ref).cuda()).cpu().numpy()
+    plan.close()
+    assert np.isnan(gb[1]).all()
+    assert np.array_equal(gb[[0, 2]], gr[[0, 2]])
