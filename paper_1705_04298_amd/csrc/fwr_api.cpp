@@ -392,6 +392,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.slopes = in;
     a.out = out;
     a.B = B;
+    a.col_shape = plan->sched;
     return fwr::multipass_run(a, extend, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
   fwr::OnchipArgs a;
@@ -662,8 +663,8 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes) {
   if (!valid(plan)) return FWR_E_STATE;
-  if (plan->multipass || plan->fourier_mp) {
-    if (threads) *threads = 256;
+  if (plan->multipass || plan->fourier_mp) {  // (the column pass's workgroup)
+    if (threads) *threads = plan->multipass && plan->sched == 1 ? 1024 : 256;
     if (frames_per_group) *frames_per_group = plan->multipass ? 2 : 1;
     if (lds_bytes) *lds_bytes = 0;
     return FWR_OK;
@@ -700,8 +701,9 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
 fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
   if (!valid(plan)) return FWR_E_STATE;
   if (schedule != 0 && schedule != 1) return FWR_E_INVAL;
-  if (schedule == 1 && (plan->multipass || plan->fourier || (plan->flags & fwr::kFlagPeriodicEach) != 0 ||
-                        !fwr::onchip_sched_ok(plan->N, plan->n)))
+  if (schedule == 1 && !plan->multipass &&
+      (plan->fourier || plan->fourier_mp || (plan->flags & fwr::kFlagPeriodicEach) != 0 ||
+       !fwr::onchip_sched_ok(plan->N, plan->n)))
     return FWR_E_UNSUPPORTED;
   plan->sched = schedule;
   return FWR_OK;
@@ -717,15 +719,18 @@ fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule) {
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 1 || B > plan->max_batch) return FWR_E_INVAL;
-  if (plan->multipass || plan->fourier_mp) {
-    if (frames_per_group) *frames_per_group = plan->multipass ? 2 : 1;
+  if (plan->fourier_mp) {
+    if (frames_per_group) *frames_per_group = 1;
     return FWR_OK;
   }
   const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
   const int n = plan->n, N = plan->N;
-  // candidate launch shapes: frame pairs per workgroup (on-chip) or frames (Fourier-domain)
+  // candidate launch shapes: frame pairs per workgroup (on-chip) or frames (Fourier-domain);
+  // the multi-pass path has one (a frame pair per field) and two column-pass shapes
+  const bool mp = plan->multipass;
   int *unit = plan->fourier ? &plan->frames : &plan->pairs;
   auto shape_ok = [&](int u) {
+    if (mp) return u == 1;
     return plan->fourier ? fwr::fourier_frames_ok(N, n, u) : fwr::onchip_pairs_ok(N, n, u, each);
   };
   // the kernels' work does not depend on the slope values: time them on zeros
@@ -741,8 +746,9 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
             hipMemsetAsync(d_in, 0, in_bytes, plan->stream) == hipSuccess;
   const int before = *unit, sched_before = plan->sched;
-  // radix schedules: both where the windowed on-chip kernel has two, else the first
-  const int n_sched = !plan->fourier && !each && fwr::onchip_sched_ok(N, n) ? 2 : 1;
+  // radix schedules: both where the windowed on-chip kernel has two, else the first; the
+  // multi-pass path's column-pass shapes (16 or 64 threads per line)
+  const int n_sched = mp || (!plan->fourier && !each && fwr::onchip_sched_ok(N, n)) ? 2 : 1;
   int best = before, best_sched = sched_before;
   float best_ms = 0.f;
   for (int pairs : kPairsOptions) {
@@ -878,6 +884,8 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   plan->multipass = true;
   plan->dmask = a.mask;
   plan->d = p.d;
+  // the column-pass shape autotuned earlier in the process for this shape, else 16 threads per line
+  plan->sched = tuned_value(plan->device, N, n, p.n_iter, p.periodic_each_iter != 0, FWR_MODEL_FRIED) / 16;
   *out = plan;
   return FWR_OK;
 }

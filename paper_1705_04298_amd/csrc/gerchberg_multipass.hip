@@ -71,10 +71,17 @@ __device__ __forceinline__ uint32_t measured(const MPArgs &a, int pair, int cm, 
   return (finite(ax) && finite(ay) ? 0u : 1u) | (finite(bx) && finite(by) ? 0u : 2u);
 }
 
-// non-finite bits of the pair, from the window row blocks' words
+// non-finite bits of the pair, from the window row blocks' words (all N/16 words are loaded
+// at once; those past the window's blocks are not written by this plan and are ignored)
 __device__ __forceinline__ uint32_t pair_bad(const MPArgs &a, int pair) {
+  const int nb = (a.o + a.n) / R - a.o / R + 1;
+  const uint32_t *w = a.bad + (size_t)pair * (NN / R);
   uint32_t bad = 0;
-  for (int b = 0; b <= (a.o + a.n) / R - a.o / R; ++b) bad |= a.bad[(size_t)pair * (NN / R) + b];
+#pragma unroll
+  for (int b = 0; b < NN / R; ++b) {
+    const uint32_t v = w[b];
+    bad |= b < nb ? v : 0u;
+  }
   return bad;
 }
 
@@ -237,8 +244,8 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
     const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
     const int idx = inw ? (m - o) * n + (nn - o) : 0;
     inp[q] = inw && a.mask[idx] != 0;
-    mx[q] = make_float2(clean(sa[idx]), hasB ? clean(sb[idx]) : 0.f);
-    my[q] = make_float2(clean(sa[plane + idx]), hasB ? clean(sb[plane + idx]) : 0.f);
+    mx[q] = make_float2(sa[idx], hasB ? sb[idx] : 0.f);
+    my[q] = make_float2(sa[plane + idx], hasB ? sb[plane + idx] : 0.f);
   }
   __syncthreads();
   float2 acc = make_float2(0.f, 0.f);
@@ -249,8 +256,10 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
     const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
     const float2 gx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
     const float2 gy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
-    const float2 ex = inp[q] ? csub(mx[q], gx) : make_float2(0.f, 0.f);
-    const float2 ey = inp[q] ? csub(my[q], gy) : make_float2(0.f, 0.f);
+    // (cleaned here, after the barrier, so that the loads above stay in flight across it)
+    const float2 mxc = make_float2(clean(mx[q].x), clean(mx[q].y)), myc = make_float2(clean(my[q].x), clean(my[q].y));
+    const float2 ex = inp[q] ? csub(mxc, gx) : make_float2(0.f, 0.f);
+    const float2 ey = inp[q] ? csub(myc, gy) : make_float2(0.f, 0.f);
     acc = cadd(acc, ex);
     eyl[rl * NN + nn] = ey;
   }
@@ -271,23 +280,32 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
 // rows outside [rlo, rhi] (and, with `border`, other than 0 and N-1) are read as zeros;
 // only rows in [wlo, whi] are written back
 // (reads the spectrum from `in`, writes it to a.spec; the two may be the same field)
-__global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float2 *in, const float *h, int rlo, int rhi,
+// TPL threads per 256-point line (the launch shape the autotuner picks): 16 (radix-16 DFTs in
+// registers, four workgroups per CU) or 64 (one wave per line, quad sub-transforms: four times
+// the waves for the same lines, for small batches)
+template <int TPL>
+__global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in, const float *h, int rlo, int rhi,
                                                       int wlo, int whi, int border) {
+  static_assert(TPL == 16 || TPL == 64, "16 or 64 threads per line");
+  constexpr int CT = R * TPL;
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
-  const int t = threadIdx.x, cl = t >> 4, r = t & 15;
+  __shared__ float2 tw[NN];  // TPL = 16: W_256^e; TPL = 64: the lane-ordered stage-A twiddles
+  __shared__ float2 tw16[16];
+  const int t = threadIdx.x, cl = t / TPL, u = t % TPL;
+  const QuadLane q(u & 3);
   const int pair = blockIdx.y, c0 = blockIdx.x * R;
-  load_tw(tw, a.tw256, t);
+  if (t < NN) tw[t] = TPL == 16 ? a.tw256[t] : twq_entry(a.tw256, t);
+  if (TPL == 64 && t < 16) tw16[t] = tw16_entry(a.tw256, t);
   const float2 *Sin = in + field(pair);
   float2 *S = a.spec + field(pair);
   // rows outside [rlo, rhi] load row rlo (a cache hit) and are replaced by zeros: every
   // load is issued first and kept unconditional, so that they are not serialised behind
   // divergent branches
-  constexpr int NL = R * NN / THREADS;
+  constexpr int NL = R * NN / CT;
   float2 v[NL];
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) {
-    const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
+    const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
     const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
     v[c_] = Sin[(size_t)(in ? row : rlo) * NN + c0 + cc];
   }
@@ -295,31 +313,43 @@ __global__ __launch_bounds__(THREADS) void col_kernel(MPArgs a, const float2 *in
   for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) {
-    const int row = (t + c_ * THREADS) / R, cc = (t + c_ * THREADS) % R;
+    const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
     const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
     L[cc * LP + pad(row)] = in ? v[c_] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_stage_a<-1>(L + cl * LP, r, tw);
-  __syncthreads();
-  fft_stage_b<-1>(L + cl * LP, r);
+  if constexpr (TPL == 16) {
+    fft_stage_a<-1>(L + cl * LP, u, tw);
+    __syncthreads();
+    fft_stage_b<-1>(L + cl * LP, u);
+  } else {
+    fft_quad_stage_a<-1>(L + cl * LP, u, tw, tw16, q);
+    __syncthreads();
+    fft_quad_stage_b<-1>(L + cl * LP, u, tw16, q);
+  }
   __syncthreads();
   const float *hc = h + (size_t)(c0 + cl) * NN;
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int p = r + R * q;
-    float2 v = L[cl * LP + pad(p)];
+  for (int i = 0; i < NN / TPL; ++i) {
+    const int p = u + TPL * i;
+    const float2 w = L[cl * LP + pad(p)];
     const float hv = hc[p];
-    L[cl * LP + pad(p)] = make_float2(v.x * hv, v.y * hv);
+    L[cl * LP + pad(p)] = make_float2(w.x * hv, w.y * hv);
   }
   __syncthreads();
-  fft_stage_b<+1>(L + cl * LP, r);
-  __syncthreads();
-  fft_stage_a<+1>(L + cl * LP, r, tw);
+  if constexpr (TPL == 16) {
+    fft_stage_b<+1>(L + cl * LP, u);
+    __syncthreads();
+    fft_stage_a<+1>(L + cl * LP, u, tw);
+  } else {
+    fft_quad_stage_b<+1>(L + cl * LP, u, tw16, q);
+    __syncthreads();
+    fft_quad_stage_a<+1>(L + cl * LP, u, tw, tw16, q);
+  }
   __syncthreads();
 #pragma unroll
-  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
-    const int i = t + c_ * THREADS;
+  for (int c_ = 0; c_ < R * NN / CT; ++c_) {  // (constant trip count: unrolled, loads batched)
+    const int i = t + c_ * CT;
     const int row = i / R, cc = i % R;
     if (row >= wlo && row <= whi) S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
   }
@@ -453,8 +483,8 @@ __global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero)
     const bool inw = unsigned(m - o) < unsigned(n) && unsigned(nn - o) < unsigned(n);
     const int idx = inw ? (m - o) * n + (nn - o) : 0;
     inp[q] = inw && a.mask[idx] != 0;
-    mx[q] = make_float2(clean(sa[idx]), clean(sb[idx]));
-    my[q] = make_float2(clean(sa[plane + idx]), clean(sb[plane + idx]));
+    mx[q] = make_float2(sa[idx], sb[idx]);
+    my[q] = make_float2(sa[plane + idx], sb[plane + idx]);
   }
   __syncthreads();
   float2 *SX = a.sx + field(pair), *SY = a.sy + field(pair);
@@ -466,9 +496,9 @@ __global__ __launch_bounds__(THREADS) void slopes_kernel(MPArgs a, int phi_zero)
     const float2 c = ph[(rl + 1) * NN + nn], d = ph[(rl + 1) * NN + np];
     float2 sx = make_float2(0.5f * ((b.x - a0.x) + (d.x - c.x)), 0.5f * ((b.y - a0.y) + (d.y - c.y)));
     float2 sy = make_float2(0.5f * ((c.x - a0.x) + (d.x - b.x)), 0.5f * ((c.y - a0.y) + (d.y - b.y)));
-    if (inp[q]) {  // measured inside the pupil (bit for bit), G phi outside
-      sx = make_float2(mx[q].x, hasB ? mx[q].y : 0.f);
-      sy = make_float2(my[q].x, hasB ? my[q].y : 0.f);
+    if (inp[q]) {  // measured inside the pupil (bit for bit; cleaned), G phi outside
+      sx = make_float2(clean(mx[q].x), hasB ? clean(mx[q].y) : 0.f);
+      sy = make_float2(clean(my[q].x), hasB ? clean(my[q].y) : 0.f);
     }
     SX[(size_t)m * NN + nn] = sx;
     SY[(size_t)m * NN + nn] = sy;
@@ -590,6 +620,12 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   const int rlo = a.o >= 2 ? a.o - 1 : 0, rhi = a.o >= 2 ? a.o + a.n + 1 : NN - 1;
   const int wb0 = wlo / R, wb1 = whi / R, rb0 = rlo / R, rb1 = rhi / R;
   const dim3 wrows(wb1 - wb0 + 1, pairs), rrows(rb1 - rb0 + 1, pairs);
+  auto col = [&](const float2 *in, const float *h, int rlo_, int rhi_, int wlo_, int whi_, int border) {
+    if (a.col_shape == 1)
+      hipLaunchKernelGGL(col_kernel<64>, rows, dim3(R * 64), 0, s, a, in, h, rlo_, rhi_, wlo_, whi_, border);
+    else
+      hipLaunchKernelGGL(col_kernel<16>, rows, dim3(R * 16), 0, s, a, in, h, rlo_, rhi_, wlo_, whi_, border);
+  };
   auto explicit_q = [&](bool phi_zero, bool fix) {
     hipLaunchKernelGGL(slopes_kernel, rows, blk, 0, s, a, phi_zero ? 1 : 0);
     if (fix) hipLaunchKernelGGL(periodic_kernel, dim3(pairs), blk, 0, s, a);
@@ -606,7 +642,7 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     // q2 is window-supported here unless per-iteration Eq. 5 made it explicit
     const bool win_in = !each || it == 0;
     const bool full_out = each || (last && explicit_final && !eq5_sums);  // phi needed on every row
-    hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, col_in, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
+    col(col_in, a.h_loop, win_in ? wlo : 0, win_in ? whi : NN - 1,
                        full_out ? 0 : rlo, full_out ? NN - 1 : rhi, 0);
     col_in = a.spec;
     if (!last && !each) {
@@ -641,7 +677,7 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     hipLaunchKernelGGL(row_fwd_kernel, wrows, blk, 0, s, a, 1, wb0, 0);
   }
   // the output is the window rows
-  hipLaunchKernelGGL(col_kernel, rows, blk, 0, s, a, a.spec, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
+  col(a.spec, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
                      whi, border ? 1 : 0);
   hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0);
   hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);

@@ -25,6 +25,7 @@ struct MPArgs {
   const uint8_t *mask;   // [n][n]
   const uint8_t *codes;  // [N][N]: out-of-pupil bits of the 4 cells around each node
   int B, n, o, n_iter, flags;
+  int col_shape = 0;     // column pass: 0 = 16 threads per 256-point line, 1 = 64 (quad sub-transforms)
 };
 
 bool multipass_supported(int N);

@@ -180,7 +180,7 @@ def test_schedule_choices_outside_the_windowed_kernel(F):
              F.Plan(78, 80, I.pupil_mask(78), max_batch=2),                    # not 2x padded
              F.Plan(10, 20, I.pupil_mask(10), max_batch=2),                    # T = 5: one schedule
              F.Plan(40, 80, I.pupil_mask(40), max_batch=2, periodic_each_iter=True),
-             F.Plan(128, 256, I.pupil_mask(128), max_batch=2)]                 # multi-pass
+             F.Plan(128, 256, I.pupil_mask(128), max_batch=2, model="sinc")]   # multi-pass, sinc
     for plan in cases:
         plan.set_schedule(0)
         with pytest.raises(F.FwrError) as e:
@@ -193,3 +193,9 @@ def test_schedule_choices_outside_the_windowed_kernel(F):
         plan.set_schedule(2)
     assert e.value.status == F.FWR_E_INVAL
     plan.close()
+    # the Fried multi-pass plan takes both column-pass shapes (16 or 64 threads per line)
+    mp = F.Plan(128, 256, I.pupil_mask(128), max_batch=2)
+    for sched in (1, 0):
+        mp.set_schedule(sched)
+        assert mp.schedule == sched
+    mp.close()

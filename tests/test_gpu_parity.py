@@ -39,11 +39,13 @@ def rel_rms(got, want):
     return np.sqrt(np.mean((got - want) ** 2)) / max(den, 1e-300)
 
 
-def run_case(F, slopes, mask, p: O.Params, what="reconstruct"):
+def run_case(F, slopes, mask, p: O.Params, what="reconstruct", schedule=None):
     n, N = p.n_sub, p.n_grid
     plan = F.Plan(n, N, mask, n_iter=p.n_iter, periodic=p.periodic,
                   periodic_each_iter=p.periodic_each_iter, gamma=p.gamma, noise_var=p.noise_var,
                   r0=p.r0, L0=p.L0, d=p.d, max_batch=max(1, slopes.shape[0]))
+    if schedule is not None:
+        plan.set_schedule(schedule)
     x = torch.from_numpy(np.ascontiguousarray(slopes, dtype=np.float32)).cuda()
     if what == "reconstruct":
         out = plan.reconstruct(x)
@@ -55,10 +57,10 @@ def run_case(F, slopes, mask, p: O.Params, what="reconstruct"):
     return res
 
 
-def check_reconstruct(F, slopes, mask, p, tag):
+def check_reconstruct(F, slopes, mask, p, tag, schedule=None):
     _flush(f"[gpu] reconstruct {tag} n={p.n_sub} N={p.n_grid} B={slopes.shape[0]} it={p.n_iter} "
-           f"per={p.periodic} each={p.periodic_each_iter} gamma={p.gamma}")
-    got = run_case(F, slopes, mask, p)
+           f"per={p.periodic} each={p.periodic_each_iter} gamma={p.gamma} schedule={schedule}")
+    got = run_case(F, slopes, mask, p, schedule=schedule)
     s32 = slopes.astype(np.float32).astype(np.float64)  # the oracle sees the same float32 inputs
     for b in range(slopes.shape[0]):
         want = O.reconstruct(s32[b], mask, p)
@@ -121,14 +123,15 @@ def test_grid_sizes_other_eq5_modes(fwr, N, n, periodic, each):
 
 
 @pytest.mark.parametrize("periodic,each,n_iter", [(False, False, 5), (True, True, 3), (True, False, 1)])
-def test_thin_border_multipass(fwr, periodic, each, n_iter):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_thin_border_multipass(fwr, periodic, each, n_iter, schedule):
     """N = 256 with a one-cell border (n = 254, o = 1): the stencil's reach wraps round the grid and
-    node row N-1 is a window row."""
+    node row N-1 is a window row; both column-pass shapes (16 and 64 threads per line)."""
     mask = I.random_mask(254, seed=254)
     slopes = I.random_slopes(2, 254, seed=7)
     p = O.Params(n_sub=254, n_grid=256, n_iter=n_iter, periodic=periodic, periodic_each_iter=each, gamma=1.0,
                  noise_var=0.01, r0=0.15, L0=25.0, d=39.0 / 254)
-    check_reconstruct(fwr, slopes, mask, p, "thin256")
+    check_reconstruct(fwr, slopes, mask, p, "thin256", schedule=schedule)
 
 
 @pytest.mark.parametrize("periodic", [False, True])
@@ -305,13 +308,45 @@ def test_elt128_multipass(fwr, n_iter, periodic, each):
                       O.Params(n_iter=n_iter, periodic=periodic, periodic_each_iter=each, **ELT), "elt")
 
 
-@pytest.mark.parametrize("periodic", [False, True])
-def test_elt128_extend(fwr, periodic):
+@pytest.mark.parametrize("n_iter,periodic,each", [(20, True, False), (3, False, False), (2, True, True)])
+def test_elt128_column_pass_64_threads_per_line(fwr, n_iter, periodic, each):
+    """The column pass's second launch shape (schedule 1: one wave per 256-point line, quads of
+    lanes doing the 16-point sub-transforms) against the oracle (the two shapes round differently:
+    each is held to the oracle's tolerance, not to the other)."""
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, 3, start=11, dtype=np.float64)
+    p = O.Params(n_iter=n_iter, periodic=periodic, periodic_each_iter=each, **ELT)
+    check_reconstruct(fwr, slopes, mask, p, "elt-q", schedule=1)
+
+
+def test_multipass_autotune_keeps_a_column_shape(fwr):
+    """The autotuner times both column-pass shapes on a multi-pass plan, keeps the faster one and
+    starts later plans of the same shape from it; results stay within the oracle's tolerance."""
+    mask = I.pupil_mask(128)
+    p = O.Params(n_iter=4, periodic=True, **ELT)
+    plan = fwr.Plan(128, 256, mask, n_iter=4, periodic=True, gamma=p.gamma, noise_var=p.noise_var,
+                    r0=p.r0, L0=p.L0, d=p.d, max_batch=8)
+    assert plan.autotune(8) == 2
+    chosen = plan.schedule
+    assert chosen in (0, 1)
+    threads, fpg, _ = plan.launch_info()
+    assert fpg == 2 and threads == (1024 if chosen == 1 else 256)
+    plan.close()
+    again = fwr.Plan(128, 256, mask, n_iter=4, periodic=True, gamma=p.gamma, noise_var=p.noise_var,
+                     r0=p.r0, L0=p.L0, d=p.d, max_batch=8)
+    assert again.schedule == chosen
+    again.close()
+    slopes = I.make_batch(I.ELT_128, 2, start=13, dtype=np.float64)
+    check_reconstruct(fwr, slopes, mask, p, "elt-tuned", schedule=chosen)
+
+
+@pytest.mark.parametrize("periodic,schedule", [(False, 0), (True, 0), (True, 1)])
+def test_elt128_extend(fwr, periodic, schedule):
     mask = I.pupil_mask(128)
     slopes = I.make_batch(I.ELT_128, 2, start=5, dtype=np.float32)
     p = O.Params(n_iter=6, periodic=periodic, **ELT)
-    _flush(f"[gpu] elt extend periodic={periodic}")
-    got = run_case(fwr, slopes, mask, p, what="extend")
+    _flush(f"[gpu] elt extend periodic={periodic} schedule={schedule}")
+    got = run_case(fwr, slopes, mask, p, what="extend", schedule=schedule)
     o = 64
     m = mask.astype(bool)
     for b in range(2):
