@@ -50,6 +50,10 @@ constexpr int kpad() { return ((9 * CIN + 31) / 32) * 32; }
 #endif
 constexpr int kTileRows = FWR_CNN_TILE_ROWS;  // output rows per step of the convolution
 constexpr int kSegTiles = 5;  // consecutive row tiles of one frame per work item
+#ifndef FWR_CNN_PIX_PAD
+#define FWR_CNN_PIX_PAD 8
+#endif
+constexpr int kPixPad = FWR_CNN_PIX_PAD;  // bf16 padding of a staged pixel vector
 
 // ------------------------------------------------------------------ forward / backward-data
 // A work item is a segment of kSegTiles row tiles (kTileRows output rows each) of one frame,
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
   // (32 k x 16 pixels), so lane l ends with channels 4 (l / 16) .. + 3 of pixel l % 16.
   // Persistent: the weights are loaded once; the workgroup walks the work items
   // blockIdx.x, blockIdx.x + gridDim.x, ...
-  constexpr int K = kpad<CIN>(), KCH = K / 32, MT = COUT / 16, CP = CIN + 8, CH = CIN / 8;
+  constexpr int K = kpad<CIN>(), KCH = K / 32, MT = COUT / 16, CP = CIN + kPixPad, CH = CIN / 8;
   constexpr int PIX_STEP = 256 / CH;  // halo pixels staged per pass of the workgroup
   extern __shared__ __attribute__((aligned(16))) uint16_t halo[];  // ring [kTileRows + 2][N + 2][CP]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t *__restrict__ 
 }
 
 template <int CIN>
-constexpr size_t halo_bytes(int N) { return size_t(kTileRows + 2) * (N + 2) * (CIN + 8) * 2; }
+constexpr size_t halo_bytes(int N) { return size_t(kTileRows + 2) * (N + 2) * (CIN + kPixPad) * 2; }
 
 // ------------------------------------------------------------------ weight gradient
 // dW[co][t*CIN + ci] += sum_p dz[p][co] x[p + off(t)][ci]; one block per frame, 32-pixel chunks.

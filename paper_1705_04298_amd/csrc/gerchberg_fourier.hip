@@ -195,43 +195,57 @@ void fourier_kernel(FourierArgs a) {
     }
     __syncthreads();  // the column sums are read before the next use of the buffers
   };
-  if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) a.resid[f] = 0.f;
-  for (int it = 0; it < a.n_iter; ++it) {
-    solve(false);
-    if (a.resid != nullptr && it == a.n_iter - 1) {
-      // in-pupil misfit of the last iteration, before step 4: ||P (s' - s0)|| / ||P s0||
-      float num = 0.f, den = 0.f;
+  // in-pupil misfit of the last iteration, before step 4: ||P (s' - s0)|| / ||P s0||
+  auto residual = [&]() {
+    float num = 0.f, den = 0.f;
 #pragma unroll
-      for (int k = 0; k < T; ++k) {
-        const bool in = in_rows && ((pup >> k) & 1u);
-        const float2 v = meas_at(k);
-        const float dx = x[k].x - v.x, dy = x[k].y - v.y;
-        num += in ? dx * dx + dy * dy : 0.f;
-        den += in ? v.x * v.x + v.y * v.y : 0.f;
-      }
-      num += dpp_xor1(num);
-      num += dpp_xor2(num);
-      den += dpp_xor1(den);
-      den += dpp_xor2(den);
-      if (j == 0) sums[line] = make_float2(num, den);
-      __syncthreads();
-      if (t == 0) {  // fixed-order sum over the lines
-        float nt = 0.f, dt = 0.f;
-        for (int m = 0; m < N; ++m) {
-          nt += sums[m].x;
-          dt += sums[m].y;
-        }
-        if (active) a.resid[f] = !(dt <= 0.f) ? sqrtf(nt / dt) : 0.f;  // (NaN stays NaN)
-      }
-      __syncthreads();  // the line sums are read before the buffer is used again
+    for (int k = 0; k < T; ++k) {
+      const bool in = in_rows && ((pup >> k) & 1u);
+      const float2 v = meas_at(k);
+      const float dx = x[k].x - v.x, dy = x[k].y - v.y;
+      num += in ? dx * dx + dy * dy : 0.f;
+      den += in ? v.x * v.x + v.y * v.y : 0.f;
     }
-    // step 4: the measurement inside the pupil, the extrapolation outside
+    num += dpp_xor1(num);
+    num += dpp_xor2(num);
+    den += dpp_xor1(den);
+    den += dpp_xor2(den);
+    if (j == 0) sums[line] = make_float2(num, den);
+    __syncthreads();
+    if (t < 64) {  // fixed-order sum over the lines: lane-wise, then a butterfly over the wave
+      float nt = 0.f, dt = 0.f;
+      for (int m = t; m < N; m += 64) {
+        nt += sums[m].x;
+        dt += sums[m].y;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        nt += __shfl_xor(nt, off);
+        dt += __shfl_xor(dt, off);
+      }
+      if (t == 0 && active) a.resid[f] = !(dt <= 0.f) ? sqrtf(nt / dt) : 0.f;  // (NaN stays NaN)
+    }
+    __syncthreads();  // the line sums are read before the buffer is used again
+  };
+  // step 4: the measurement inside the pupil, the extrapolation outside
+  auto replace = [&]() {
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       const bool in = in_rows && ((pup >> k) & 1u);
       const float2 v = meas_at(k);
       x[k] = make_float2(select_bits(in, v.x, x[k].x), select_bits(in, v.y, x[k].y));
     }
+  };
+  if (a.resid != nullptr && a.n_iter == 0 && t == 0 && active) a.resid[f] = 0.f;
+  for (int it = 0; it < a.n_iter; ++it) {
+    solve(false);
+    if (a.resid != nullptr && it == a.n_iter - 1) {
+      residual();
+      // (keeps the residual's reads of the measurement apart from step 4's: shared, they cost
+      // the loop 69 spilled VGPRs)
+      asm volatile("" ::: "memory");
+    }
+    replace();
     if (a.flags & kFourierPeriodicEach) eq5();
   }
 
