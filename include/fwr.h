@@ -224,6 +224,22 @@ fwr_status fwr_reconstruct_start(fwr_plan_t plan, const float *d_slopes, const f
 fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B);
 
 /* ------------------------------------------------------------------------
+ * Forward slope model (the sensor of a simulation loop).
+ *
+ * fwr_fried_slopes: the plan's Fried slope model (Sec. 2, the geometry the reconstruction
+ * inverts) applied to node phases: s_x(i, j) = (phi(i, j+1) - phi(i, j) + phi(i+1, j+1)
+ * - phi(i+1, j)) / 2 and s_y(i, j) = (phi(i+1, j) - phi(i, j) + phi(i+1, j+1) -
+ * phi(i, j+1)) / 2, plus d_noise when it is not NULL, zero on the subapertures the
+ * plan's mask marks invalid.  d_phase: float[B][n+1][n+1] (row = y); d_noise:
+ * float[B][2][n][n] or NULL; d_slopes: float[B][2][n][n], written.  Plans of the Fried
+ * model on any grid (FWR_E_UNSUPPORTED for FWR_MODEL_SINC: that model needs the
+ * continuous phase, not node values).  B = 0 is a no-op; B > max_batch or a NULL
+ * phase / slope pointer is FWR_E_INVAL.  Asynchronous on the plan's stream.
+ */
+fwr_status fwr_fried_slopes(fwr_plan_t plan, const float *d_phase, const float *d_noise, float *d_slopes,
+                            int32_t B);
+
+/* ------------------------------------------------------------------------
  * Mixed batches and synthetic frames.
  *
  * fwr_reconstruct_group: several plans (grid sizes, iteration counts) with their

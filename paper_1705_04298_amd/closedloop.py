@@ -16,8 +16,9 @@ The figure of merit is the residual phase rms on the pupil nodes (piston removed
 `steps - settle` steps (Sec. 4.2 exposes the camera for 200 closed-loop steps) and the
 corresponding Strehl ratio in K band (Marechal approximation, phase scaled by 0.5 / 2.2 um).
 
-The screen motion, the sensor, the mirror update and the statistics are tensor plumbing around the
-library calls (the simulated system, not the method).
+The sensor is the library's Fried slope model (`fwr_fried_slopes`); the screen motion, the noise
+draw, the mirror update and the statistics are tensor plumbing around the library calls (the
+simulated system, not the method).
 
     python -m paper_1705_04298_amd.closedloop --loops 1024 --steps 400
 """
@@ -73,6 +74,10 @@ class Loop:
             self.ext = torch.empty((self.B, 2, N, N), device="cuda")
         else:
             self.plan = fwr.Plan(n, N, mask, n_iter=n_iter, periodic=periodic, max_batch=self.B)
+        # the sensor's slope model (a Fried plan of the same geometry; the Hudgin path's plan has
+        # n_iter = 0 and serves as well)
+        self.sensor = self.plan
+        self.slopes = torch.empty((self.B, 2, n, n), device="cuda")
         self.dm = torch.zeros((self.B, n + 1, n + 1), device="cuda")
         self.rec = torch.empty((self.B, n + 1, n + 1), device="cuda")
         self.gen = torch.Generator(device="cuda").manual_seed(seed)
@@ -87,12 +92,12 @@ class Loop:
         return row[:, :, : self.n + 1].float().contiguous()
 
     def measure(self, res, noise=None):
+        """The sensor: the library's Fried slope model of the residual phase, plus white noise,
+        zero on invalid subapertures (fwr_fried_slopes)."""
         torch = self.torch
-        a, b, c, e = res[:, :-1, :-1], res[:, :-1, 1:], res[:, 1:, :-1], res[:, 1:, 1:]
-        s = torch.stack([0.5 * ((b - a) + (e - c)), 0.5 * ((c - a) + (e - b))], dim=1)
         if noise is None:
-            noise = torch.randn(s.shape, device="cuda", generator=self.gen) * self.sigma
-        return ((s + noise) * self.mask).contiguous()
+            noise = torch.randn((self.B, 2, self.n, self.n), device="cuda", generator=self.gen) * self.sigma
+        return self.sensor.fried_slopes(res.contiguous(), noise.contiguous(), self.slopes)
 
     def reconstruct(self, slopes):
         if self.method == "hudgin":

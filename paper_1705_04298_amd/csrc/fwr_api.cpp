@@ -522,6 +522,18 @@ fwr_status fwr_generate(fwr_plan_t plan, uint64_t seed, uint64_t first_frame, ui
   return e == hipSuccess ? FWR_OK : FWR_E_DEVICE;
 }
 
+fwr_status fwr_fried_slopes(fwr_plan_t plan, const float *d_phase, const float *d_noise, float *d_slopes,
+                            int32_t B) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (plan->fourier || plan->fourier_mp || plan->dmask == nullptr) return FWR_E_UNSUPPORTED;
+  if (B < 0 || B > plan->max_batch) return FWR_E_INVAL;
+  if (B == 0) return FWR_OK;
+  if (d_phase == nullptr || d_slopes == nullptr) return FWR_E_INVAL;
+  return fwr::fried_slopes_launch(d_phase, d_noise, plan->dmask, d_slopes, B, plan->n, plan->stream) == hipSuccess
+             ? FWR_OK
+             : FWR_E_DEVICE;
+}
+
 fwr_status fwr_hudgin_extend(fwr_plan_t plan, const float *d_slopes, float *d_ext, int32_t B) {
   if (!valid(plan)) return FWR_E_STATE;
   if (plan->hudgin_src == nullptr) return FWR_E_UNSUPPORTED;

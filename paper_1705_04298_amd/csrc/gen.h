@@ -21,4 +21,9 @@ struct GenArgs {
 bool gen_supported(int N);
 hipError_t gen_launch(int N, const GenArgs &a, hipStream_t s);
 
+// The Fried slope model applied to node phases: slopes[B][2][n][n] of phase[B][n+1][n+1], plus
+// noise[B][2][n][n] when given, zero on invalid subapertures (mask[n][n] on the device).
+hipError_t fried_slopes_launch(const float *phase, const float *noise, const uint8_t *mask, float *slopes, int B,
+                               int n, hipStream_t s);
+
 }  // namespace fwr

@@ -141,7 +141,39 @@ __global__ void counter_add_kernel(uint64_t *c, uint64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c += v;
 }
 
+// Fried slopes of node phases (Sec. 2; the model the reconstruction inverts), one frame per
+// blockIdx.y, cells in grid-stride order: s_x = (phi(m, n+1) - phi(m, n) + phi(m+1, n+1) -
+// phi(m+1, n)) / 2, s_y with rows and columns exchanged; plus the noise; zero outside the pupil.
+__global__ __launch_bounds__(256) void fried_slopes_kernel(const float *phase, const float *noise,
+                                                           const uint8_t *mask, float *slopes, int n) {
+  const int f = blockIdx.y, n1 = n + 1, plane = n * n;
+  const float *p = phase + (size_t)f * n1 * n1;
+  float *sa = slopes + (size_t)f * 2 * plane;
+  const float *na = noise ? noise + (size_t)f * 2 * plane : nullptr;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < plane; idx += gridDim.x * 256) {
+    const int i = idx / n, c = idx - i * n;
+    const float a = p[i * n1 + c], b = p[i * n1 + c + 1], cc = p[(i + 1) * n1 + c], e = p[(i + 1) * n1 + c + 1];
+    float sx = 0.5f * ((b - a) + (e - cc)), sy = 0.5f * ((cc - a) + (e - b));
+    if (na) {
+      sx += na[idx];
+      sy += na[plane + idx];
+    }
+    const bool v = mask[idx] != 0;
+    sa[idx] = v ? sx : 0.f;
+    sa[plane + idx] = v ? sy : 0.f;
+  }
+}
+
 }  // namespace gen
+
+hipError_t fried_slopes_launch(const float *phase, const float *noise, const uint8_t *mask, float *slopes, int B,
+                               int n, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const int blocks = (n * n + 255) / 256;
+  hipLaunchKernelGGL(gen::fried_slopes_kernel, dim3(blocks < 64 ? blocks : 64, B), dim3(256), 0, s, phase, noise,
+                     mask, slopes, n);
+  return hipGetLastError();
+}
 
 #define FWR_GEN_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(128)
 

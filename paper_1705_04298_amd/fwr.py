@@ -36,7 +36,7 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
             "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned", "fwr_plan_set_schedule",
             "fwr_plan_get_schedule", "fwr_reconstruct_learned_noalloc", "fwr_cnn_loss_grad",
-            "fwr_cnn_backward_grad")
+            "fwr_cnn_backward_grad", "fwr_fried_slopes")
 CNN_PARAMS = 47714
 
 
@@ -137,6 +137,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_reconstruct_learned_noalloc.restype = ctypes.c_int
     lib.fwr_hudgin_extend.argtypes = [vp, vp, vp, i32]
     lib.fwr_hudgin_extend.restype = ctypes.c_int
+    lib.fwr_fried_slopes.argtypes = [vp, vp, vp, vp, i32]
+    lib.fwr_fried_slopes.restype = ctypes.c_int
     lib.fwr_plan_set_group.argtypes = [vp, i32]
     lib.fwr_plan_set_group.restype = ctypes.c_int
     lib.fwr_plan_set_schedule.argtypes = [vp, i32]
@@ -339,6 +341,24 @@ class Plan:
         st = load().fwr_hudgin_extend(self._h, ctypes.c_void_p(slopes.data_ptr()), ctypes.c_void_p(out.data_ptr()), B)
         if st != FWR_OK:
             raise FwrError(st, "fwr_hudgin_extend")
+        return out
+
+    def fried_slopes(self, phase, noise=None, out=None):
+        """The plan's Fried slope model on node phases [B, n+1, n+1] (+ noise [B, 2, n, n]), zero on
+        invalid subapertures: slopes [B, 2, n, n] (fwr_fried_slopes)."""
+        import torch
+        B = phase.shape[0]
+        self._check(phase, (B, self.n_sub + 1, self.n_sub + 1), "phase")
+        if noise is not None:
+            self._check(noise, (B, 2, self.n_sub, self.n_sub), "noise")
+        if out is None:
+            out = torch.empty((B, 2, self.n_sub, self.n_sub), device=phase.device, dtype=torch.float32)
+        self._check(out, (B, 2, self.n_sub, self.n_sub), "out")
+        st = load().fwr_fried_slopes(self._h, ctypes.c_void_p(phase.data_ptr()),
+                                     ctypes.c_void_p(noise.data_ptr() if noise is not None else 0),
+                                     ctypes.c_void_p(out.data_ptr()), B)
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_fried_slopes")
         return out
 
     def generate(self, B: int, seed: int, first_frame: int = 0, r0: float = 0.15, L0: float = 25.0,

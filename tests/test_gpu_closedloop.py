@@ -46,3 +46,38 @@ def test_loop_follows_the_oracle(method, n_iter, periodic):
         err = np.sqrt(np.mean((res_gpu - res) ** 2) / np.mean(res ** 2))
         assert err <= 1e-5, (t, err)
     loop.close()
+
+
+def test_fried_slope_model_call():
+    """fwr_fried_slopes (the harness's sensor) against the oracle's Fried transfer function applied
+    to the node phase embedded in a periodic grid (the stencil touches only window nodes), plus the
+    noise, zero on invalid subapertures; FWR_E_UNSUPPORTED on a lenslet-averaging plan."""
+    from oracle import fwr_oracle as O
+    from paper_1705_04298_amd import fwr
+    fwr.load()
+    n, N, B = 40, 80, 3
+    mask = I.pupil_mask(n)
+    rng = np.random.default_rng(8)
+    phase = rng.standard_normal((B, n + 1, n + 1)).astype(np.float32)
+    noise = (0.1 * rng.standard_normal((B, 2, n, n))).astype(np.float32)
+    plan = fwr.Plan(n, N, mask, max_batch=B)
+    ph = torch.from_numpy(phase).cuda()
+    clean = plan.fried_slopes(ph).cpu().numpy().astype(np.float64)
+    noisy = plan.fried_slopes(ph, torch.from_numpy(noise).cuda()).cpu().numpy().astype(np.float64)
+    plan.close()
+    Gx, Gy = O.fried_model(N)
+    m = mask.astype(bool)
+    for b in range(B):
+        grid = np.zeros((N, N))
+        grid[: n + 1, : n + 1] = phase[b]
+        F = O.dft2(grid)
+        want = [np.real(O.idft2(G * F))[:n, :n] for G in (Gx, Gy)]
+        for c in range(2):
+            assert np.abs(clean[b, c][m] - want[c][m]).max() < 2e-6
+            assert np.all(clean[b, c][~m] == 0) and np.all(noisy[b, c][~m] == 0)
+            assert np.abs(noisy[b, c][m] - (want[c][m] + noise[b, c][m])).max() < 2e-6
+    sinc = fwr.Plan(n, N, mask, max_batch=B, model="sinc")
+    with pytest.raises(fwr.FwrError) as e:
+        sinc.fried_slopes(ph)
+    assert e.value.status == fwr.FWR_E_UNSUPPORTED
+    sinc.close()
