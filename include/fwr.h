@@ -243,15 +243,17 @@ fwr_status fwr_fried_slopes(fwr_plan_t plan, const float *d_phase, const float *
  * Mixed batches and synthetic frames.
  *
  * fwr_reconstruct_group: several plans (grid sizes, iteration counts) with their
- * batches in one call.  The items run concurrently on library-owned streams
- * that fork from and join back into `stream` (hipStream_t; captured as parallel
- * branches when `stream` is being captured into a HIP graph).  Each item is as
+ * batches in one call.  The items run concurrently: one on `stream`
+ * (hipStream_t; the first multi-pass item, else the first item), the others
+ * on library-owned streams that fork from and join back into `stream`
+ * (captured as parallel branches when `stream` is being captured into a HIP
+ * graph).  Each item is as
  * fwr_reconstruct (d_start / d_resid optional, as fwr_reconstruct_start).  A
  * plan may appear in one item only (its workspace serves one batch at a time);
  * one call at a time per process.  Every item is checked before anything is
  * enqueued (the first failing item's status; nothing runs).  The first call
- * creates max(8, n_work) streams and events on the current device, later calls
- * with more items add streams; a call made while `stream` is being captured
+ * creates max(8, n_work - 1) streams and events on the current device, later
+ * calls with more items add streams; a call made while `stream` is being captured
  * that would need new streams gives FWR_E_UNSUPPORTED, so make one call with
  * at least as many items before capturing.  After a failed launch the other
  * branches still join `stream` (FWR_E_DEVICE).

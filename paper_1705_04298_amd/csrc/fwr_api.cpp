@@ -453,9 +453,17 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
   const hipStream_t main = static_cast<hipStream_t>(stream);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(main, &cap) != hipSuccess) return FWR_E_DEVICE;
-  // the streams and events are made outside any capture (at least 8 on the first call)
-  const int want = n_work > 8 ? n_work : 8;
-  if ((int)pool.size() < n_work && cap != hipStreamCaptureStatusNone) return FWR_E_UNSUPPORTED;
+  // One item runs on the caller's stream, the others on library streams forked from it.  HIP gives
+  // a process a few hardware queues (4 by default) and binds each stream to one of them; streams
+  // that share a queue run one after the other.  n - 1 library streams beside
+  // the caller's leave n = 4 items on four queues where the process holds no other streams; where
+  // it does, the queue least likely to be shared is the caller's (often the first stream bound),
+  // so the caller's stream takes the item with the longest chain of launches (the first multi-pass
+  // plan, else the first item), enqueued after the others so their single launches start first.
+  // The streams and events are made outside any capture (at least 8 on the first call).
+  const int need = n_work - 1;
+  const int want = need > 8 ? need : 8;
+  if ((int)pool.size() < need && cap != hipStreamCaptureStatusNone) return FWR_E_UNSUPPORTED;
   while ((int)pool.size() < want) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return FWR_E_DEVICE;
@@ -466,19 +474,34 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FWR_E_DEVICE;
     evs.push_back(e);
   }
-  hipEvent_t fork = evs[want];
-  if (hipEventRecord(fork, main) != hipSuccess) return FWR_E_DEVICE;
-  fwr_status status = FWR_OK;
-  int forked = 0;
-  for (int i = 0; i < n_work; ++i) {
-    if (hipStreamWaitEvent(pool[i], fork, 0) != hipSuccess) {
-      status = FWR_E_DEVICE;
+  int lead = 0;
+  for (int i = 0; i < n_work; ++i)
+    if (work[i].plan->multipass || work[i].plan->fourier_mp) {
+      lead = i;
       break;
     }
-    forked = i + 1;
+  hipEvent_t fork = evs[want];
+  if (need > 0 && hipEventRecord(fork, main) != hipSuccess) return FWR_E_DEVICE;
+  fwr_status status = FWR_OK;
+  int forked = 0;
+  bool fork_ok = true;
+  for (int i = 0; i < n_work; ++i) {
+    if (i == lead) continue;
+    const hipStream_t st = pool[forked];
+    if (hipStreamWaitEvent(st, fork, 0) != hipSuccess) {
+      status = FWR_E_DEVICE;
+      fork_ok = false;
+      break;
+    }
+    ++forked;
     const fwr_work &w = work[i];
-    const fwr_status st = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, pool[i], true);
-    if (st != FWR_OK && status == FWR_OK) status = st;
+    const fwr_status r = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, st, true);
+    if (r != FWR_OK && status == FWR_OK) status = r;
+  }
+  if (fork_ok) {
+    const fwr_work &w = work[lead];
+    const fwr_status r = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, main, true);
+    if (r != FWR_OK && status == FWR_OK) status = r;
   }
   // every forked branch joins back into the caller's stream, also after a failed launch
   for (int i = 0; i < forked; ++i)
