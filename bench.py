@@ -285,7 +285,7 @@ def elt_main(args):
     plan = fwr.Plan(n, N, I.pupil_mask(n), n_iter=n_iter, periodic=True, gamma=1.0,
                     noise_var=0.05 ** 2, r0=0.15, L0=25.0, d=39.0 / n, max_batch=B)
     if not args.no_autotune:
-        plan.autotune(B)  # the column pass's shape: 16 or 64 threads per 256-point line
+        plan.autotune(B)  # the loop's launch shape: per pass (16 or 64 threads per line) or persistent
     x = torch.from_numpy(slopes).cuda()
     out = torch.empty((B, n + 1, n + 1), device="cuda", dtype=torch.float32)
     for _ in range(args.warmup):
@@ -300,12 +300,13 @@ def elt_main(args):
     ms = e0.elapsed_time(e1) / args.steps
     alg_bytes = B * (n_iter * 2 * 2 ** 20 + 2 * 2 ** 16)
     tpl = 64 if plan.schedule == 1 else 16
+    loop_shape = "one persistent launch" if plan.schedule == 2 else "one launch per pass"
     plan.close()
     print(json.dumps({"metric": "frames/s (128x128 SH, 256x256 grid, 20 Gerchberg iters)",
                       "value": B / (ms / 1e3), "unit": "frames/s", "ms_per_step": ms, "steps": args.steps,
                       "dtype": "f32", "data": "synthetic",
                       "config": {"workload": f"{B} frames 128x128 -> 256x256, 20 iterations + Eq.5 + MMSE",
-                                 "column_pass_threads_per_line": tpl},
+                                 "column_pass_threads_per_line": tpl, "loop": loop_shape},
                       "roofline": {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": 8000.0,
                                    "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / 8e12, "traffic": None}}),
           flush=True)

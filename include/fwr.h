@@ -164,20 +164,27 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
  * first.  Both compute the exact DFT and round differently (each within the
  * parity tolerance).  Schedule 1 exists for the windowed kernel of 2x-padded plans
  * (n = N/2, N >= 24, no per-iteration Eq. 5; FWR_E_UNSUPPORTED otherwise,
- * FWR_E_INVAL for other values); their calls with start values or the
- * extended-slope output take schedule 0.  On Fried plans of the multi-pass
- * path (N = 256) the two schedules are the column pass's launch shapes: 0 = 16
- * threads per 256-point line (radix-16 DFTs in registers, 256-thread workgroups),
- * 1 = 64 threads per line (one wave per line, quads of lanes doing the 16-point
- * sub-transforms, 1024-thread workgroups: four times the waves for the same lines).
- * Plans start from the schedule autotuned earlier in the process for the same
- * shape, else 0. */
+ * FWR_E_INVAL for values other than 0, 1, 2); their calls with start values or
+ * the extended-slope output take schedule 0.  On Fried plans of the multi-pass
+ * path (N = 256) the schedules are launch shapes of the loop: 0 = one launch per
+ * pass, the column pass with 16 threads per 256-point line (radix-16 DFTs in
+ * registers, 256-thread workgroups); 1 = the same with 64 threads per line (one
+ * wave per line, quads of lanes doing the 16-point sub-transforms, 1024-thread
+ * workgroups: four times the waves for the same lines); 2 = the loop's column
+ * passes and fused row steps in one persistent launch (288-thread workgroups that
+ * take column tiles and row blocks from a counter and wait, through per-pair
+ * counts in the plan's workspace, for the previous step of their own frame pair
+ * only; the same arithmetic as 0, bit for bit).  Schedule 2 applies to calls with
+ * at least two iterations and no per-iteration Eq. 5 (others run as 0); a wait
+ * that exceeds about a second gives up and writes the call's frames as NaN.
+ * Schedule 2 is FWR_E_UNSUPPORTED on other plans.  Plans start from the schedule
+ * autotuned earlier in the process for the same shape, else 0. */
 fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule);
 fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule);
 
 /* Autotuner: times every frames-per-workgroup choice of the plan on B frames (B <=
  * max_batch; device scratch is allocated and freed here), with each radix schedule
- * the plan allows (on the Fried multi-pass path: both column-pass shapes), on the
+ * the plan allows (on the Fried multi-pass path: its three launch shapes), on the
  * plan's stream, synchronously; keeps the fastest pair in the plan and for later
  * plans of the same shape, and returns the frames per workgroup in
  * *frames_per_group (may be NULL; the schedule: fwr_plan_get_schedule).  Not for
@@ -186,7 +193,8 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
 
 /* Launch shape of the reconstruction kernel, for reporting: threads per
  * workgroup, frames per workgroup, LDS bytes per workgroup (static + dynamic).
- * Multi-pass plans report the column pass's workgroup and 0 LDS bytes. */
+ * Multi-pass plans report the column pass's workgroup (the persistent loop's
+ * with schedule 2) and 0 LDS bytes. */
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes);
 

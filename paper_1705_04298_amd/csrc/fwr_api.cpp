@@ -698,8 +698,8 @@ fwr_status fwr_set_stream(fwr_plan_t plan, void *stream) {
 fwr_status fwr_plan_launch_info(fwr_plan_t plan, int32_t *threads, int32_t *frames_per_group,
                                 int32_t *lds_bytes) {
   if (!valid(plan)) return FWR_E_STATE;
-  if (plan->multipass || plan->fourier_mp) {  // (the column pass's workgroup)
-    if (threads) *threads = plan->multipass && plan->sched == 1 ? 1024 : 256;
+  if (plan->multipass || plan->fourier_mp) {  // (the column pass's workgroup; the persistent loop's)
+    if (threads) *threads = plan->multipass && plan->sched == 1 ? 1024 : (plan->multipass && plan->sched == 2 ? 288 : 256);
     if (frames_per_group) *frames_per_group = plan->multipass ? 2 : 1;
     if (lds_bytes) *lds_bytes = 0;
     return FWR_OK;
@@ -735,7 +735,8 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
 
 fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
   if (!valid(plan)) return FWR_E_STATE;
-  if (schedule != 0 && schedule != 1) return FWR_E_INVAL;
+  if (schedule < 0 || schedule > 2) return FWR_E_INVAL;
+  if (schedule == 2 && !plan->multipass) return FWR_E_UNSUPPORTED;
   if (schedule == 1 && !plan->multipass &&
       (plan->fourier || plan->fourier_mp || (plan->flags & fwr::kFlagPeriodicEach) != 0 ||
        !fwr::onchip_sched_ok(plan->N, plan->n)))
@@ -782,8 +783,9 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
             hipMemsetAsync(d_in, 0, in_bytes, plan->stream) == hipSuccess;
   const int before = *unit, sched_before = plan->sched;
   // radix schedules: both where the windowed on-chip kernel has two, else the first; the
-  // multi-pass path's column-pass shapes (16 or 64 threads per line)
-  const int n_sched = mp || (!plan->fourier && !each && fwr::onchip_sched_ok(N, n)) ? 2 : 1;
+  // multi-pass path's launch shapes (column passes of 16 or 64 threads per line, or the loop as
+  // one persistent launch)
+  const int n_sched = mp ? 3 : (!plan->fourier && !each && fwr::onchip_sched_ok(N, n) ? 2 : 1);
   int best = before, best_sched = sched_before;
   float best_ms = 0.f;
   for (int pairs : kPairsOptions) {
@@ -899,6 +901,7 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   a.f0 = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes);
   a.sums = reinterpret_cast<float2 *>(w + 4 * pairs * fbytes + pairs * (size_t)(n + 1) * N * sizeof(float2));
   a.bad = reinterpret_cast<uint32_t *>(a.sums + pairs * 2 * (size_t)N);
+  a.ctl = a.bad + pairs * (size_t)(N / 16);
   a.h_loop = reinterpret_cast<const float *>(mem);
   a.h_final = reinterpret_cast<const float *>(mem + off_hf);
   a.tw256 = reinterpret_cast<const float2 *>(mem + off_tw);

@@ -29,6 +29,8 @@
 // 16 k1 + k2 then holds frequency k1 + 16 k2 (digit-reversed); the filter
 // table is laid out in that order and the inverse undoes it.  Lines are
 // padded by one element every 16, plus one (273 per line), to spread LDS banks.
+#include <algorithm>
+
 #include "fft256.h"
 #include "multipass.h"
 
@@ -57,6 +59,30 @@ __device__ __forceinline__ bool finite(float v) { return (__float_as_uint(v) & 0
 __device__ __forceinline__ float clean(float v) { return finite(v) ? v : 0.f; }
 __device__ __forceinline__ float nan_f() { return __uint_as_float(0x7fc00000u); }
 
+// Loads and stores of the spectrum fields that workgroups of the persistent loop kernel hand to
+// one another within the launch (COH): relaxed atomics at agent scope, i.e. accesses coherent
+// across the XCDs' L2 caches (the L2s of a multi-XCD device are not coherent with each other
+// within a kernel; plain accesses may hit a stale line).  The other kernels use plain accesses.
+template <bool COH>
+__device__ __forceinline__ float2 ld2(const float2 *p) {
+  if constexpr (COH) {
+    const unsigned long long v = __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<float2 *>(p)),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float(uint32_t(v)), __uint_as_float(uint32_t(v >> 32)));
+  } else {
+    return *p;
+  }
+}
+template <bool COH>
+__device__ __forceinline__ void st2(float2 *p, float2 v) {
+  if constexpr (COH) {
+    const unsigned long long b = uint64_t(__float_as_uint(v.x)) | (uint64_t(__float_as_uint(v.y)) << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
+
 // measured (s_x, s_y) of cell (cm, cn) for frames A (real) and B (imag), cleaned; returns
 // the frames' non-finite bits (1: A, 2: B)
 __device__ __forceinline__ uint32_t measured(const MPArgs &a, int pair, int cm, int cn, float2 &sx, float2 &sy) {
@@ -76,7 +102,7 @@ __device__ __forceinline__ uint32_t measured(const MPArgs &a, int pair, int cm, 
 __device__ __forceinline__ uint32_t pair_bad(const MPArgs &a, int pair) {
   const int nb = (a.o + a.n) / R - a.o / R + 1;
   const uint32_t *w = a.bad + (size_t)pair * (NN / R);
-  uint32_t bad = 0;
+  uint32_t bad = a.loop_err != nullptr && *a.loop_err != 0 ? 3u : 0u;  // (the loop gave up: every frame)
 #pragma unroll
   for (int b = 0; b < NN / R; ++b) {
     const uint32_t v = w[b];
@@ -283,19 +309,16 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
 // TPL threads per 256-point line (the launch shape the autotuner picks): 16 (radix-16 DFTs in
 // registers, four workgroups per CU) or 64 (one wave per line, quad sub-transforms: four times
 // the waves for the same lines, for small batches)
-template <int TPL>
-__global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in, const float *h, int rlo, int rhi,
-                                                      int wlo, int whi, int border) {
-  static_assert(TPL == 16 || TPL == 64, "16 or 64 threads per line");
+// One 16-column tile (the body of col_kernel; the persistent loop kernel runs it with COH and
+// with threads past the tile's R * TPL idle).  L: R padded lines; tw, tw16 staged by the caller.
+template <int TPL, bool COH>
+__device__ __forceinline__ void col_tile(const MPArgs &a, float2 *L, const float2 *tw, const float2 *tw16, int t,
+                                         int pair, int c0, const float2 *in, const float *h, int rlo, int rhi,
+                                         int wlo, int whi, int border) {
   constexpr int CT = R * TPL;
-  __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];  // TPL = 16: W_256^e; TPL = 64: the lane-ordered stage-A twiddles
-  __shared__ float2 tw16[16];
-  const int t = threadIdx.x, cl = t / TPL, u = t % TPL;
+  const bool act = t < CT;
+  const int cl = t / TPL, u = t % TPL;
   const QuadLane q(u & 3);
-  const int pair = blockIdx.y, c0 = blockIdx.x * R;
-  if (t < NN) tw[t] = TPL == 16 ? a.tw256[t] : twq_entry(a.tw256, t);
-  if (TPL == 64 && t < 16) tw16[t] = tw16_entry(a.tw256, t);
   const float2 *Sin = in + field(pair);
   float2 *S = a.spec + field(pair);
   // rows outside [rlo, rhi] load row rlo (a cache hit) and are replaced by zeros: every
@@ -303,56 +326,75 @@ __global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in
   // divergent branches
   constexpr int NL = R * NN / CT;
   float2 v[NL];
+  if (act) {
 #pragma unroll
-  for (int c_ = 0; c_ < NL; ++c_) {
-    const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
-    const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
-    v[c_] = Sin[(size_t)(in ? row : rlo) * NN + c0 + cc];
-  }
+    for (int c_ = 0; c_ < NL; ++c_) {
+      const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
+      const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
+      v[c_] = ld2<COH>(Sin + (size_t)(in ? row : rlo) * NN + c0 + cc);
+    }
 #pragma unroll
-  for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
+    for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
 #pragma unroll
-  for (int c_ = 0; c_ < NL; ++c_) {
-    const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
-    const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
-    L[cc * LP + pad(row)] = in ? v[c_] : make_float2(0.f, 0.f);
+    for (int c_ = 0; c_ < NL; ++c_) {
+      const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
+      const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
+      L[cc * LP + pad(row)] = in ? v[c_] : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   if constexpr (TPL == 16) {
-    fft_stage_a<-1>(L + cl * LP, u, tw);
+    if (act) fft_stage_a<-1>(L + cl * LP, u, tw);
     __syncthreads();
-    fft_stage_b<-1>(L + cl * LP, u);
+    if (act) fft_stage_b<-1>(L + cl * LP, u);
   } else {
     fft_quad_stage_a<-1>(L + cl * LP, u, tw, tw16, q);
     __syncthreads();
     fft_quad_stage_b<-1>(L + cl * LP, u, tw16, q);
   }
   __syncthreads();
-  const float *hc = h + (size_t)(c0 + cl) * NN;
+  if (act) {
+    const float *hc = h + (size_t)(c0 + cl) * NN;
 #pragma unroll
-  for (int i = 0; i < NN / TPL; ++i) {
-    const int p = u + TPL * i;
-    const float2 w = L[cl * LP + pad(p)];
-    const float hv = hc[p];
-    L[cl * LP + pad(p)] = make_float2(w.x * hv, w.y * hv);
+    for (int i = 0; i < NN / TPL; ++i) {
+      const int p = u + TPL * i;
+      const float2 w = L[cl * LP + pad(p)];
+      const float hv = hc[p];
+      L[cl * LP + pad(p)] = make_float2(w.x * hv, w.y * hv);
+    }
   }
   __syncthreads();
   if constexpr (TPL == 16) {
-    fft_stage_b<+1>(L + cl * LP, u);
+    if (act) fft_stage_b<+1>(L + cl * LP, u);
     __syncthreads();
-    fft_stage_a<+1>(L + cl * LP, u, tw);
+    if (act) fft_stage_a<+1>(L + cl * LP, u, tw);
   } else {
     fft_quad_stage_b<+1>(L + cl * LP, u, tw16, q);
     __syncthreads();
     fft_quad_stage_a<+1>(L + cl * LP, u, tw, tw16, q);
   }
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int c_ = 0; c_ < R * NN / CT; ++c_) {  // (constant trip count: unrolled, loads batched)
-    const int i = t + c_ * CT;
-    const int row = i / R, cc = i % R;
-    if (row >= wlo && row <= whi) S[(size_t)row * NN + c0 + cc] = L[cc * LP + pad(row)];
+    for (int c_ = 0; c_ < R * NN / CT; ++c_) {  // (constant trip count: unrolled, loads batched)
+      const int i = t + c_ * CT;
+      const int row = i / R, cc = i % R;
+      if (row >= wlo && row <= whi) st2<COH>(S + (size_t)row * NN + c0 + cc, L[cc * LP + pad(row)]);
+    }
   }
+}
+
+template <int TPL>
+__global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in, const float *h, int rlo, int rhi,
+                                                      int wlo, int whi, int border) {
+  static_assert(TPL == 16 || TPL == 64, "16 or 64 threads per line");
+  __shared__ float2 L[R * LP];
+  __shared__ float2 tw[NN];  // TPL = 16: W_256^e; TPL = 64: the lane-ordered stage-A twiddles
+  __shared__ float2 tw16[16];
+  const int t = threadIdx.x;
+  if (t < NN) tw[t] = TPL == 16 ? a.tw256[t] : twq_entry(a.tw256, t);
+  if (TPL == 64 && t < 16) tw16[t] = tw16_entry(a.tw256, t);
+  col_tile<TPL, false>(a, L, tw, tw16, t, blockIdx.y, blockIdx.x * R, in, h, rlo, rhi, wlo, whi, border);
 }
 
 // ---------------------------------------------------------------- inverse rows
@@ -384,25 +426,23 @@ __global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
 }
 
 // ---------------------------------------------------------------- inverse rows + next forward rows
-// One loop step between two column passes when phi is needed only by the next stencil: a
-// window block takes the spectrum rows m0-1 .. m0+16, runs their inverse row FFTs (phi rows,
-// kept in LDS), then the stencil (as row_fwd mode 1) and the forward row FFTs of its 16 rows.
-// The blocks' halo rows overlap, so the result goes to `out`, not back to a.spec.
 constexpr int FT = (R + 2) * 16;  // 18 lines of 16 threads
-__global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, int b0) {
-  __shared__ float2 L[(R + 2) * LP];
-  __shared__ float2 tw[NN];
-  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
-  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
+// One window block (the body of row_inv_fwd_kernel; the persistent loop kernel runs it with COH).
+// L: R + 2 padded lines; tw staged by the caller.
+template <bool COH>
+__device__ __forceinline__ void row_inv_fwd_block(const MPArgs &a, float2 *L, const float2 *tw, int t, int pair,
+                                                  int m0, float2 *out) {
+  const int rl = t >> 4, r = t & 15;
   const bool own = rl < R;  // the threads of lines 16 and 17 transform but own no output row
   const int m = m0 + (own ? rl : 0);
-  if (t < NN) load_tw(tw, a.tw256, t);
   const float2 *S = a.spec + field(pair);
+  constexpr int NL = (R + 2) * NN / FT;
+  float2 v[NL];  // (every load issued before the first LDS store)
 #pragma unroll
-  for (int c_ = 0; c_ < (R + 2) * NN / FT; ++c_) {  // (constant trip count: unrolled, loads batched)
+  for (int c_ = 0; c_ < NL; ++c_) {  // (constant trip count: unrolled, loads batched)
     const int i = t + c_ * FT;
     const int row = i / NN, p = i % NN;
-    L[row * LP + pad(p)] = S[(size_t)((m0 - 1 + row) & (NN - 1)) * NN + p];
+    v[c_] = ld2<COH>(S + (size_t)((m0 - 1 + row) & (NN - 1)) * NN + p);
   }
   const bool win_row = own && m >= a.o && m <= a.o + a.n;
   const float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
@@ -415,6 +455,11 @@ __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, 
       f0v[q] = F0[fr + r + R * q];
       cv[q] = a.codes[m * NN + r + R * q];
     }
+  }
+#pragma unroll
+  for (int c_ = 0; c_ < NL; ++c_) {
+    const int i = t + c_ * FT;
+    L[(i / NN) * LP + pad(i % NN)] = v[c_];
   }
   __syncthreads();
   fft_stage_b<+1>(L + rl * LP, r);
@@ -451,7 +496,104 @@ __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, 
   if (t < NN) {
     float2 *D = out + field(pair);
 #pragma unroll
-    for (int row = 0; row < R; ++row) D[(size_t)(m0 + row) * NN + t] = L[row * LP + pad(t)];
+    for (int row = 0; row < R; ++row) st2<COH>(D + (size_t)(m0 + row) * NN + t, L[row * LP + pad(t)]);
+  }
+}
+
+// One loop step between two column passes when phi is needed only by the next stencil: a
+// window block takes the spectrum rows m0-1 .. m0+16, runs their inverse row FFTs (phi rows,
+// kept in LDS), then the stencil (as row_fwd mode 1) and the forward row FFTs of its 16 rows.
+// The blocks' halo rows overlap, so the result goes to `out`, not back to a.spec.
+__global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, int b0) {
+  __shared__ float2 L[(R + 2) * LP];
+  __shared__ float2 tw[NN];
+  const int t = threadIdx.x;
+  if (t < NN) load_tw(tw, a.tw256, t);
+  row_inv_fwd_block<false>(a, L, tw, t, blockIdx.y, (blockIdx.x + b0) * R, out);
+}
+
+// ---------------------------------------------------------------- persistent loop
+// The pruned loop's column passes and fused row steps, C_0, RF_0, C_1, ..., RF_{K-2}, C_{K-1}
+// (K = n_iter), as one launch of resident workgroups that take work items in that order from a
+// counter: item = (step, pair, 16-column tile or window row block).  An item waits until every
+// item of its pair in the previous step is done (a per-pair count), so pairs move through the
+// steps independently and one pair's loads overlap another's transforms, without a grid-wide
+// barrier between the steps.  Items are taken in order and wait only on earlier items, taken by
+// workgroups that are running, so the launch cannot deadlock whatever the number of resident
+// workgroups.  A wait that exceeds a fixed bound sets the error word; every workgroup then
+// stops, and the frames are written as NaN (pair_bad).  The counters are zeroed by
+// loop_reset_kernel before the launch.
+struct LoopArgs {
+  uint32_t *ctl;          // [0] next item, [1] error, [64 (pair + 1)] items of the pair done (one
+                          // 256-byte line per count: the waiting workgroups poll them)
+  int pairs, nr, wb0;     // frame pairs; window row blocks per pair and the first one
+  int wlo, whi;           // rows the column passes read (the window rows)
+  int rlo, rhi;           // rows they write back (the stencil's reach)
+  int last_wlo, last_whi; // rows the last column pass writes back
+};
+
+constexpr int kLoopSpin = 1 << 20;  // polls of a count before the wait is given up (~1 s)
+constexpr int kCtlStride = 64;      // words between two counts
+
+__global__ void loop_reset_kernel(uint32_t *ctl, int pairs) {
+  for (int i = threadIdx.x; i < kCtlStride * (pairs + 1); i += blockDim.x) ctl[i] = 0u;
+}
+
+__global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  // (4 waves per SIMD: 3 workgroups per CU, as the LDS allows)
+  __shared__ float2 L[(R + 2) * LP];
+  __shared__ float2 tw[NN];
+  __shared__ int s_item;
+  const int t = threadIdx.x;
+  if (t < NN) load_tw(tw, a.tw256, t);
+  const int per = R + l.nr;                          // items of one pair in one loop step (C + RF)
+  const int nc = l.pairs * R;                        // C items of a step (16 tiles per pair)
+  const int total = (a.n_iter - 1) * l.pairs * per + nc;
+  uint32_t *next = l.ctl, *err = l.ctl + 1, *done = l.ctl + kCtlStride;
+  int nxt = 0;
+  if (t == 0) nxt = int(atomicAdd(next, 1u));
+  for (;;) {
+    if (t == 0) {
+      int item = nxt;
+      if (item < total) {
+        nxt = int(atomicAdd(next, 1u));  // (the next item is taken while this one runs)
+        const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
+        const int pair = rem < nc ? rem / R : (rem - nc) / l.nr;
+        const uint32_t need = uint32_t(k * per + (rem < nc ? 0 : R));
+        int spin = 0;
+        while (__hip_atomic_load(done + kCtlStride * pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (((++spin & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ||
+              spin > kLoopSpin) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            item = -1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);  // (polls spaced out: they share the memory path with the items)
+        }
+      }
+      s_item = item;
+    }
+    __syncthreads();
+    const int item = s_item;
+    if (item < 0 || item >= total) break;
+    // (the thread index laundered per item, so that the bodies' address arithmetic is not hoisted
+    // out of the item loop and held in registers across it)
+    int tl = t;
+    asm volatile("" : "+v"(tl));
+    const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
+    int pair;
+    if (rem < nc) {
+      pair = rem / R;
+      const bool last = k == a.n_iter - 1;
+      col_tile<16, true>(a, L, tw, nullptr, tl, pair, (rem % R) * R, k == 0 ? a.spec : a.sy, a.h_loop, l.wlo,
+                         l.whi, last ? l.last_wlo : l.rlo, last ? l.last_whi : l.rhi, 0);
+    } else {
+      pair = (rem - nc) / l.nr;
+      row_inv_fwd_block<true>(a, L, tw, tl, pair, (l.wb0 + (rem - nc) % l.nr) * R, a.sy);
+    }
+    // every store of the item is complete (seen at agent scope) before the pair's count moves
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (t == 0) __hip_atomic_fetch_add(done + kCtlStride * pair, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -596,7 +738,25 @@ size_t multipass_workspace_bytes(int N, int n, int max_batch) {
   const size_t pairs = (size_t)(max_batch + 1) / 2;
   const size_t f = (size_t)N * N * sizeof(float2);
   return pairs * (4 * f + (size_t)(n + 1) * N * sizeof(float2) + 2 * (size_t)N * sizeof(float2) +
-                 (size_t)(N / mp::R) * sizeof(uint32_t));
+                 (size_t)(N / mp::R) * sizeof(uint32_t)) +
+         multipass_ctl_words(max_batch) * sizeof(uint32_t);
+}
+
+size_t multipass_ctl_words(int max_batch) { return mp::kCtlStride * ((size_t)(max_batch + 1) / 2 + 1); }
+
+// resident workgroups of the persistent loop kernel on the current device (occupancy x CUs)
+static int loop_grid() {
+  static int grid[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (grid[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mp::loop_kernel, mp::FT, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    grid[dev] = (per_cu > 0 ? per_cu : 1) * cus;
+  }
+  return grid[dev];
 }
 
 bool multipass_supported(int N) { return N == mp::NN; }
@@ -637,7 +797,33 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   // until after the loop), which the next column pass reads back into the spectrum field.
   float2 *const spec2 = a.sy;
   const float2 *col_in = a.spec;
-  for (int it = 0; it < a.n_iter; ++it) {
+  // launch shape 2: the loop's column passes and fused row steps in one persistent launch
+  const int lgrid = a.col_shape == 2 && !each && a.n_iter >= 2 ? loop_grid() : 0;
+  if (lgrid > 0) {
+    const bool full_last = explicit_final && !eq5_sums;  // (as full_out of the last iteration below)
+    LoopArgs l{};
+    l.ctl = a.ctl;
+    l.pairs = pairs;
+    l.nr = wb1 - wb0 + 1;
+    l.wb0 = wb0;
+    l.wlo = wlo;
+    l.whi = whi;
+    l.rlo = rlo;
+    l.rhi = rhi;
+    l.last_wlo = full_last ? 0 : rlo;
+    l.last_whi = full_last ? NN - 1 : rhi;
+    const long total = (long)(a.n_iter - 1) * pairs * (R + l.nr) + (long)pairs * R;
+    hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(256), 0, s, a.ctl, pairs);
+    // resident workgroups, at most half the items of one loop step (more only wait: measured)
+    const long cap = std::min<long>(lgrid, (long)pairs * (R + l.nr) / 2);
+    hipLaunchKernelGGL(loop_kernel, dim3((unsigned)std::max<long>(cap, 1)), dim3(FT), 0, s, a, l);
+    a.loop_err = a.ctl + 1;  // read by the output kernels (pair_bad)
+    if (full_last)
+      hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
+    else
+      hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0);
+  }
+  for (int it = 0; it < (lgrid > 0 ? 0 : a.n_iter); ++it) {
     const bool last = it == a.n_iter - 1;
     // q2 is window-supported here unless per-iteration Eq. 5 made it explicit
     const bool win_in = !each || it == 0;

@@ -24,12 +24,16 @@ struct MPArgs {
   const float2 *tw256;   // W_256^e, e = 0..255
   const uint8_t *mask;   // [n][n]
   const uint8_t *codes;  // [N][N]: out-of-pupil bits of the 4 cells around each node
+  uint32_t *ctl;         // work counters of the persistent loop kernel
+  const uint32_t *loop_err = nullptr;  // set by the launcher after a persistent loop: its error word
   int B, n, o, n_iter, flags;
-  int col_shape = 0;     // column pass: 0 = 16 threads per 256-point line, 1 = 64 (quad sub-transforms)
+  int col_shape = 0;     // launch shape: 0 = column pass with 16 threads per 256-point line, 1 = 64
+                         // (quad sub-transforms), 2 = the loop as one persistent launch (16 threads)
 };
 
 bool multipass_supported(int N);
 size_t multipass_workspace_bytes(int N, int n, int max_batch);
+size_t multipass_ctl_words(int max_batch);
 hipError_t multipass_run(const MPArgs &a, bool extend, hipStream_t s);
 struct GenArgs;
 hipError_t multipass_generate(const MPArgs &a, const GenArgs &g, hipStream_t s);

@@ -42,8 +42,10 @@ def rel_rms(got, want):
     return np.sqrt(np.mean((got - want) ** 2) / max(np.mean(want ** 2), 1e-300))
 
 
-def test_elt128_batch_of_128_sampled(F):
-    _flush("[gpu] 128 x 128x128 -> 256x256, 20 iterations")
+@pytest.mark.parametrize("schedule", [0, 2])
+def test_elt128_batch_of_128_sampled(F, schedule):
+    """Both launch shapes the autotuner picks between at this size (launch per pass, persistent loop)."""
+    _flush(f"[gpu] 128 x 128x128 -> 256x256, 20 iterations, schedule {schedule}")
     B, n, N = 128, 128, 256
     rng = np.random.default_rng(12)
     base = I.make_batch(I.ELT_128, 8, start=40, dtype=np.float32)
@@ -54,6 +56,7 @@ def test_elt128_batch_of_128_sampled(F):
                  L0=25.0, d=39.0 / n)
     plan = F.Plan(n, N, mask, n_iter=20, periodic=True, gamma=1.0, noise_var=p.noise_var, r0=p.r0, L0=p.L0,
                   d=p.d, max_batch=B)
+    plan.set_schedule(schedule)
     got = plan.reconstruct(torch.from_numpy(slopes).cuda()).cpu().numpy().astype(np.float64)
     plan.close()
     for b in (0, 61, 126, 127):

@@ -190,12 +190,17 @@ def test_schedule_choices_outside_the_windowed_kernel(F):
         plan.close()
     plan = F.Plan(40, 80, I.pupil_mask(40), max_batch=2)
     with pytest.raises(F.FwrError) as e:
-        plan.set_schedule(2)
+        plan.set_schedule(3)
     assert e.value.status == F.FWR_E_INVAL
+    with pytest.raises(F.FwrError) as e:  # the persistent loop is a multi-pass launch shape
+        plan.set_schedule(2)
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+    assert plan.schedule == 0
     plan.close()
-    # the Fried multi-pass plan takes both column-pass shapes (16 or 64 threads per line)
+    # the Fried multi-pass plan takes its three launch shapes (column passes of 16 or 64 threads
+    # per line, the persistent loop)
     mp = F.Plan(128, 256, I.pupil_mask(128), max_batch=2)
-    for sched in (1, 0):
+    for sched in (2, 1, 0):
         mp.set_schedule(sched)
         assert mp.schedule == sched
     mp.close()

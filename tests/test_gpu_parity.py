@@ -123,10 +123,11 @@ def test_grid_sizes_other_eq5_modes(fwr, N, n, periodic, each):
 
 
 @pytest.mark.parametrize("periodic,each,n_iter", [(False, False, 5), (True, True, 3), (True, False, 1)])
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_thin_border_multipass(fwr, periodic, each, n_iter, schedule):
     """N = 256 with a one-cell border (n = 254, o = 1): the stencil's reach wraps round the grid and
-    node row N-1 is a window row; both column-pass shapes (16 and 64 threads per line)."""
+    node row N-1 is a window row; every launch shape (column passes of 16 and 64 threads per line,
+    the loop as one persistent launch)."""
     mask = I.random_mask(254, seed=254)
     slopes = I.random_slopes(2, 254, seed=7)
     p = O.Params(n_sub=254, n_grid=256, n_iter=n_iter, periodic=periodic, periodic_each_iter=each, gamma=1.0,
@@ -319,8 +320,35 @@ def test_elt128_column_pass_64_threads_per_line(fwr, n_iter, periodic, each):
     check_reconstruct(fwr, slopes, mask, p, "elt-q", schedule=1)
 
 
+@pytest.mark.parametrize("n_iter,periodic,each", [(20, True, False), (3, False, False), (2, True, True)])
+def test_elt128_persistent_loop(fwr, n_iter, periodic, each):
+    """Schedule 2: the loop's column passes and fused row steps as one persistent launch whose
+    workgroups hand the spectra to one another (per-pair counts) against the oracle; with Eq. 5 after
+    every iteration the plan keeps the launch-per-pass loop."""
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, 5, start=17, dtype=np.float64)
+    p = O.Params(n_iter=n_iter, periodic=periodic, periodic_each_iter=each, **ELT)
+    check_reconstruct(fwr, slopes, mask, p, "elt-persistent", schedule=2)
+
+
+@pytest.mark.parametrize("B,n_iter,periodic", [(5, 20, True), (7, 2, True), (4, 3, False), (6, 1, True),
+                                               (3, 5, False), (64, 10, True)])
+def test_persistent_loop_same_bits_as_launch_per_pass(fwr, B, n_iter, periodic):
+    """The persistent loop runs the same column-tile and row-block arithmetic as the launch-per-pass
+    loop (16 threads per line): bit-identical phases and extended slopes, odd and even batches."""
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, B, start=3, dtype=np.float32)
+    p = O.Params(n_iter=n_iter, periodic=periodic, **ELT)
+    _flush(f"[gpu] persistent loop vs launch per pass B={B} n_iter={n_iter} periodic={periodic}")
+    for what in ("reconstruct", "extend"):
+        a = run_case(fwr, slopes, mask, p, what=what, schedule=0)
+        b = run_case(fwr, slopes, mask, p, what=what, schedule=2)
+        assert np.isfinite(b).all()
+        assert np.array_equal(a, b), what
+
+
 def test_multipass_autotune_keeps_a_column_shape(fwr):
-    """The autotuner times both column-pass shapes on a multi-pass plan, keeps the faster one and
+    """The autotuner times the three launch shapes of a multi-pass plan, keeps the fastest and
     starts later plans of the same shape from it; results stay within the oracle's tolerance."""
     mask = I.pupil_mask(128)
     p = O.Params(n_iter=4, periodic=True, **ELT)
@@ -328,9 +356,9 @@ def test_multipass_autotune_keeps_a_column_shape(fwr):
                     r0=p.r0, L0=p.L0, d=p.d, max_batch=8)
     assert plan.autotune(8) == 2
     chosen = plan.schedule
-    assert chosen in (0, 1)
+    assert chosen in (0, 1, 2)
     threads, fpg, _ = plan.launch_info()
-    assert fpg == 2 and threads == (1024 if chosen == 1 else 256)
+    assert fpg == 2 and threads == {0: 256, 1: 1024, 2: 288}[chosen]
     plan.close()
     again = fwr.Plan(128, 256, mask, n_iter=4, periodic=True, gamma=p.gamma, noise_var=p.noise_var,
                      r0=p.r0, L0=p.L0, d=p.d, max_batch=8)
@@ -340,7 +368,7 @@ def test_multipass_autotune_keeps_a_column_shape(fwr):
     check_reconstruct(fwr, slopes, mask, p, "elt-tuned", schedule=chosen)
 
 
-@pytest.mark.parametrize("periodic,schedule", [(False, 0), (True, 0), (True, 1)])
+@pytest.mark.parametrize("periodic,schedule", [(False, 0), (True, 0), (True, 1), (True, 2), (False, 2)])
 def test_elt128_extend(fwr, periodic, schedule):
     mask = I.pupil_mask(128)
     slopes = I.make_batch(I.ELT_128, 2, start=5, dtype=np.float32)
