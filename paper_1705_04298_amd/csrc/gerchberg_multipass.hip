@@ -40,6 +40,8 @@ namespace mp {
 
 __device__ __forceinline__ size_t field(int pair) { return (size_t)pair * NN * NN; }
 
+constexpr int kCtlStride = 64;  // words between two work counts of the persistent loop (ctl)
+
 __device__ __forceinline__ void load_tw(float2 *tw, const float2 *g, int t) {
   tw[t] = g[t];  // 256 entries, 256 threads
 }
@@ -228,6 +230,12 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   fft_stage_b<-1>(L + rl * LP, r);
   __syncthreads();
   if (mode == 0 && t == 0) a.bad[(size_t)pair * (NN / R) + blockIdx.x] = badw;  // (b0 = the first window block)
+  // the start pass also zeroes the persistent loop's counters: the pair's count, and with pair 0
+  // the item counter and the error word
+  if (mode == 0 && blockIdx.x == 0 && t < kCtlStride) {
+    a.ctl[(size_t)kCtlStride * (pair + 1) + t] = 0u;
+    if (pair == 0) a.ctl[t] = 0u;
+  }
   float2 *S = a.spec + field(pair);
 #pragma unroll
   for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
@@ -522,7 +530,7 @@ __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, 
 // workgroups that are running, so the launch cannot deadlock whatever the number of resident
 // workgroups.  A wait that exceeds a fixed bound sets the error word; every workgroup then
 // stops, and the frames are written as NaN (pair_bad).  The counters are zeroed by
-// loop_reset_kernel before the launch.
+// the start pass (row_fwd_kernel, mode 0) before the launch.
 struct LoopArgs {
   uint32_t *ctl;          // [0] next item, [1] error, [64 (pair + 1)] items of the pair done (one
                           // 256-byte line per count: the waiting workgroups poll them)
@@ -533,11 +541,7 @@ struct LoopArgs {
 };
 
 constexpr int kLoopSpin = 1 << 20;  // polls of a count before the wait is given up (~1 s)
-constexpr int kCtlStride = 64;      // words between two counts
 
-__global__ void loop_reset_kernel(uint32_t *ctl, int pairs) {
-  for (int i = threadIdx.x; i < kCtlStride * (pairs + 1); i += blockDim.x) ctl[i] = 0u;
-}
 
 __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  // (4 waves per SIMD: 3 workgroups per CU, as the LDS allows)
   __shared__ float2 L[(R + 2) * LP];
@@ -813,7 +817,6 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     l.last_wlo = full_last ? 0 : rlo;
     l.last_whi = full_last ? NN - 1 : rhi;
     const long total = (long)(a.n_iter - 1) * pairs * (R + l.nr) + (long)pairs * R;
-    hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(256), 0, s, a.ctl, pairs);
     // resident workgroups, at most half the items of one loop step (more only wait: measured)
     const long cap = std::min<long>(lgrid, (long)pairs * (R + l.nr) / 2);
     hipLaunchKernelGGL(loop_kernel, dim3((unsigned)std::max<long>(cap, 1)), dim3(FT), 0, s, a, l);
