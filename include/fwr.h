@@ -182,6 +182,14 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
 fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule);
 fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule);
 
+/* Watchdog of the persistent loop (schedule 2 of Fried multi-pass plans): the
+ * number of polls (about 1 us each) a workgroup waits for the previous step of
+ * its frame pair before the call gives up; a call that gives up writes every frame
+ * of its output as NaN, and the next call starts afresh.  Default 2^20 (about a
+ * second: a wait that long means the device is shared with work that holds it).
+ * polls in [1, 2^24] (FWR_E_INVAL otherwise); FWR_E_UNSUPPORTED on other plans. */
+fwr_status fwr_plan_set_wait_limit(fwr_plan_t plan, int32_t polls);
+
 /* Autotuner: times every frames-per-workgroup choice of the plan on B frames (B <=
  * max_batch; device scratch is allocated and freed here), with each radix schedule
  * the plan allows (on the Fried multi-pass path: its three launch shapes), on the

@@ -745,6 +745,14 @@ fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
   return FWR_OK;
 }
 
+fwr_status fwr_plan_set_wait_limit(fwr_plan_t plan, int32_t polls) {
+  if (!valid(plan)) return FWR_E_STATE;
+  if (!plan->multipass) return FWR_E_UNSUPPORTED;
+  if (polls < 1 || polls > (1 << 24)) return FWR_E_INVAL;
+  plan->mp.wait_limit = polls;
+  return FWR_OK;
+}
+
 fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule) {
   if (!valid(plan)) return FWR_E_STATE;
   if (schedule == nullptr) return FWR_E_INVAL;

@@ -528,8 +528,8 @@ __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, 
 // steps independently and one pair's loads overlap another's transforms, without a grid-wide
 // barrier between the steps.  Items are taken in order and wait only on earlier items, taken by
 // workgroups that are running, so the launch cannot deadlock whatever the number of resident
-// workgroups.  A wait that exceeds a fixed bound sets the error word; every workgroup then
-// stops, and the frames are written as NaN (pair_bad).  The counters are zeroed by
+// workgroups.  A wait longer than a.wait_limit polls (~1 us each; default 2^20) sets the error
+// word; every workgroup then stops, and the frames are written as NaN (pair_bad).  The counters are zeroed by
 // the start pass (row_fwd_kernel, mode 0) before the launch.
 struct LoopArgs {
   uint32_t *ctl;          // [0] next item, [1] error, [64 (pair + 1)] items of the pair done (one
@@ -540,7 +540,6 @@ struct LoopArgs {
   int last_wlo, last_whi; // rows the last column pass writes back
 };
 
-constexpr int kLoopSpin = 1 << 20;  // polls of a count before the wait is given up (~1 s)
 
 
 __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  // (4 waves per SIMD: 3 workgroups per CU, as the LDS allows)
@@ -566,7 +565,7 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  //
         int spin = 0;
         while (__hip_atomic_load(done + kCtlStride * pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           if (((++spin & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ||
-              spin > kLoopSpin) {
+              spin > a.wait_limit) {
             __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             item = -1;
             break;

@@ -27,6 +27,7 @@ struct MPArgs {
   uint32_t *ctl;         // work counters of the persistent loop kernel
   const uint32_t *loop_err = nullptr;  // set by the launcher after a persistent loop: its error word
   int B, n, o, n_iter, flags;
+  int wait_limit = 1 << 20;  // polls of a count before the persistent loop gives up
   int col_shape = 0;     // launch shape: 0 = column pass with 16 threads per 256-point line, 1 = 64
                          // (quad sub-transforms), 2 = the loop as one persistent launch (16 threads)
 };

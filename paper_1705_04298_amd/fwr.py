@@ -36,7 +36,7 @@ EXPORTED = ("fwr_plan", "fwr_extend", "fwr_reconstruct", "fwr_destroy", "fwr_set
             "fwr_reconstruct_group", "fwr_generate", "fwr_cnn_set_stream", "fwr_plan_set_group",
             "fwr_plan_autotune", "fwr_hudgin_extend", "fwr_reconstruct_learned", "fwr_plan_set_schedule",
             "fwr_plan_get_schedule", "fwr_reconstruct_learned_noalloc", "fwr_cnn_loss_grad",
-            "fwr_cnn_backward_grad", "fwr_fried_slopes")
+            "fwr_cnn_backward_grad", "fwr_fried_slopes", "fwr_plan_set_wait_limit")
 CNN_PARAMS = 47714
 
 
@@ -143,6 +143,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fwr_plan_set_group.restype = ctypes.c_int
     lib.fwr_plan_set_schedule.argtypes = [vp, i32]
     lib.fwr_plan_set_schedule.restype = ctypes.c_int
+    lib.fwr_plan_set_wait_limit.argtypes = [vp, i32]
+    lib.fwr_plan_set_wait_limit.restype = ctypes.c_int
     lib.fwr_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     lib.fwr_plan_get_schedule.restype = ctypes.c_int
     lib.fwr_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
@@ -394,10 +396,17 @@ class Plan:
             raise FwrError(st, "fwr_plan_set_group")
 
     def set_schedule(self, schedule: int):
-        """Radix schedule of the in-lane DFTs (0 or 1; fwr_plan_set_schedule)."""
+        """Radix schedule of the in-lane DFTs, or the multi-pass loop's launch shape (0, 1, 2;
+        fwr_plan_set_schedule)."""
         st = load().fwr_plan_set_schedule(self._h, int(schedule))
         if st != FWR_OK:
             raise FwrError(st, "fwr_plan_set_schedule")
+
+    def set_wait_limit(self, polls: int):
+        """Watchdog of the persistent multi-pass loop, in polls (fwr_plan_set_wait_limit)."""
+        st = load().fwr_plan_set_wait_limit(self._h, int(polls))
+        if st != FWR_OK:
+            raise FwrError(st, "fwr_plan_set_wait_limit")
 
     @property
     def schedule(self) -> int:

@@ -331,6 +331,45 @@ def test_elt128_persistent_loop(fwr, n_iter, periodic, each):
     check_reconstruct(fwr, slopes, mask, p, "elt-persistent", schedule=2)
 
 
+def test_persistent_loop_watchdog(fwr):
+    """A wait limit of one poll makes the persistent loop give up as soon as an item finds its pair's
+    previous step unfinished (forced from the host; every kernel still ends normally): the call's
+    frames are then all NaN, never partly computed, and the next call with the default limit is
+    exact again (the start pass clears the error word)."""
+    B = 128
+    mask = I.pupil_mask(128)
+    slopes = I.make_batch(I.ELT_128, 8, start=21, dtype=np.float32)
+    x = torch.from_numpy(np.ascontiguousarray(np.concatenate([slopes] * (B // 8)))).cuda()
+    p = O.Params(n_iter=20, periodic=True, **ELT)
+    plan = fwr.Plan(128, 256, mask, n_iter=20, periodic=True, gamma=p.gamma, noise_var=p.noise_var, r0=p.r0,
+                    L0=p.L0, d=p.d, max_batch=B)
+    _flush("[gpu] persistent loop watchdog")
+    plan.set_schedule(0)
+    ref = plan.reconstruct(x).cpu().numpy()
+    plan.set_schedule(2)
+    for bad in (0, 1 << 25):
+        with pytest.raises(fwr.FwrError) as e:
+            plan.set_wait_limit(bad)
+        assert e.value.status == fwr.FWR_E_INVAL
+    plan.set_wait_limit(1)
+    gave_up = 0
+    for _ in range(3):
+        got = plan.reconstruct(x).cpu().numpy()
+        if np.isnan(got).all():
+            gave_up += 1
+        else:
+            assert np.array_equal(got, ref)
+    assert gave_up > 0  # (128 frames: some item always finds its dependency unfinished)
+    plan.set_wait_limit(1 << 20)
+    assert np.array_equal(plan.reconstruct(x).cpu().numpy(), ref)
+    plan.close()
+    onchip = fwr.Plan(40, 80, I.pupil_mask(40), max_batch=2)
+    with pytest.raises(fwr.FwrError) as e:
+        onchip.set_wait_limit(100)
+    assert e.value.status == fwr.FWR_E_UNSUPPORTED
+    onchip.close()
+
+
 @pytest.mark.parametrize("B,n_iter,periodic", [(5, 20, True), (7, 2, True), (4, 3, False), (6, 1, True),
                                                (3, 5, False), (64, 10, True)])
 def test_persistent_loop_same_bits_as_launch_per_pass(fwr, B, n_iter, periodic):
