@@ -19,7 +19,21 @@ constexpr int THREADS = 256;
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-// 256-point line FFT in LDS (L = padded line), thread r = 0..15 of the line's 16.
+// Stage-A twiddle table, staged in LDS by the caller: entry 17 r + k = W_256^(r k) (k < 16, entry
+// 17 r + 16 unused), so that thread r reads its 15 twiddles at one base address with immediate
+// offsets, and the 16 threads of a line, reading the same k, hit 16 different bank pairs (odd row
+// pitch). TW_RK entries, staged by threads t < TW_RK.
+constexpr int TW_RK = 17 * 16;
+__device__ __forceinline__ float2 tw_rk_entry(const float2 *tw256, int t) {
+  const int r = t / 17, k = t % 17;
+  return tw256[(r * k) & 255];
+}
+// the whole table, by the nt threads of a workgroup (t = 0..nt-1)
+__device__ __forceinline__ void stage_tw_rk(float2 *tw, const float2 *tw256, int t, int nt) {
+  for (int i = t; i < TW_RK; i += nt) tw[i] = tw_rk_entry(tw256, i);
+}
+
+// 256-point line FFT in LDS (L = padded line), thread r = 0..15 of the line's 16; tw: tw_rk_entry.
 // The caller separates stages with workgroup barriers (all lines of a block
 // are transformed together).
 template <int DIR>
@@ -30,14 +44,14 @@ __device__ __forceinline__ void fft_stage_a(float2 *L, int r, const float2 *tw) 
     for (int a = 0; a < R; ++a) v[a] = L[pad(R * a + r)];
     dft<R, -1>(v);
 #pragma unroll
-    for (int k = 1; k < R; ++k) v[k] = cmul(v[k], tw[(r * k) & (NN - 1)]);
+    for (int k = 1; k < R; ++k) v[k] = cmul(v[k], tw[17 * r + k]);
 #pragma unroll
     for (int k = 0; k < R; ++k) L[pad(R * k + r)] = v[k];
   } else {
 #pragma unroll
     for (int k = 0; k < R; ++k) v[k] = L[pad(R * k + r)];
 #pragma unroll
-    for (int k = 1; k < R; ++k) v[k] = cmul_conj(v[k], tw[(r * k) & (NN - 1)]);
+    for (int k = 1; k < R; ++k) v[k] = cmul_conj(v[k], tw[17 * r + k]);
     dft<R, +1>(v);
 #pragma unroll
     for (int a = 0; a < R; ++a) L[pad(R * a + r)] = v[a];

@@ -867,11 +867,14 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
     const int i = cm - o, jj = cn - o;
     return i >= 0 && i < n && jj >= 0 && jj < n && mask[(size_t)i * n + jj] != 0;
   };
-  std::vector<uint8_t> codes((size_t)N * N);
+  // node codes packed per thread of the row passes: node (m, r + 16 q) in bits 4q..4q+3 of word 16 m + r
+  std::vector<uint64_t> codes((size_t)N * 16, 0u);
   for (int m = 0; m < N; ++m)
-    for (int nn = 0; nn < N; ++nn)
-      codes[(size_t)m * N + nn] = uint8_t((in_pupil(m, nn) ? 0 : 1) | (in_pupil(m - 1, nn - 1) ? 0 : 2) |
-                                          (in_pupil(m, nn - 1) ? 0 : 4) | (in_pupil(m - 1, nn) ? 0 : 8));
+    for (int nn = 0; nn < N; ++nn) {
+      const uint64_t c = uint64_t((in_pupil(m, nn) ? 0 : 1) | (in_pupil(m - 1, nn - 1) ? 0 : 2) |
+                                  (in_pupil(m, nn - 1) ? 0 : 4) | (in_pupil(m - 1, nn) ? 0 : 8));
+      codes[(size_t)m * 16 + nn % 16] |= c << (4 * (nn / 16));
+    }
 
   auto *plan = new (std::nothrow) fwr_plan_s();
   if (plan == nullptr) return FWR_E_NOMEM;
@@ -880,8 +883,9 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
     return FWR_E_DEVICE;
   }
   const size_t b_h = hl.size() * sizeof(float), b_tw = tw.size() * sizeof(float2);
-  const size_t off_hf = b_h, off_tw = 2 * b_h, off_mask = off_tw + b_tw, off_codes = off_mask + mask.size();
-  const size_t off_ws = (off_codes + codes.size() + 255) & ~size_t(255);
+  const size_t off_hf = b_h, off_tw = 2 * b_h, off_codes = off_tw + b_tw;
+  const size_t b_codes = codes.size() * sizeof(uint64_t), off_mask = off_codes + b_codes;
+  const size_t off_ws = (off_mask + mask.size() + 255) & ~size_t(255);
   const size_t ws = fwr::multipass_workspace_bytes(N, n, p.max_batch);
   char *mem = nullptr;
   if (hipMalloc(reinterpret_cast<void **>(&mem), off_ws + ws) != hipSuccess) {
@@ -892,7 +896,7 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   if (e == hipSuccess) e = hipMemcpy(mem + off_hf, hf.data(), b_h, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(mem + off_tw, tw.data(), b_tw, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(mem + off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(mem + off_codes, codes.data(), codes.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(mem + off_codes, codes.data(), b_codes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(mem);
     delete plan;
@@ -914,7 +918,7 @@ fwr_status plan_multipass(const fwr_params &p, fwr_plan_t *out) {
   a.h_final = reinterpret_cast<const float *>(mem + off_hf);
   a.tw256 = reinterpret_cast<const float2 *>(mem + off_tw);
   a.mask = reinterpret_cast<const uint8_t *>(mem + off_mask);
-  a.codes = reinterpret_cast<const uint8_t *>(mem + off_codes);
+  a.codes = reinterpret_cast<const uint64_t *>(mem + off_codes);
   a.n = n;
   a.o = o;
   a.n_iter = p.n_iter;

@@ -55,11 +55,11 @@ __device__ __forceinline__ bool in_pupil(const FSArgs &a, int m, int c) {
 // rows m0 .. m0 + 15 of frame blockIdx.y, row block blockIdx.x + b0
 __global__ __launch_bounds__(THREADS) void rows_kernel(FSArgs a, int mode, int b0, int fix) {
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   __shared__ float red[R * R];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int f = blockIdx.y, rb = blockIdx.x + b0, m0 = rb * R;
-  tw[t] = a.tw256[t];
+  stage_tw_rk(tw, a.tw256, t, THREADS);
   constexpr int PASSES = R * NN / THREADS;  // one grid row per pass of the block
   if (mode == kInit || mode == kInitStore) {
 #pragma unroll
@@ -176,10 +176,10 @@ __device__ __forceinline__ int mirror_pos(int p) {
 
 __global__ __launch_bounds__(THREADS) void cols_kernel(FSArgs a, int fin) {
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   const int t = threadIdx.x, cl = t >> 4, r = t & 15;
   const int f = blockIdx.y, g = blockIdx.x;
-  tw[t] = a.tw256[t];
+  stage_tw_rk(tw, a.tw256, t, THREADS);
   float2 *S = a.spec + fld(f);
   constexpr int NL = R * NN / THREADS;
   {

@@ -42,8 +42,22 @@ __device__ __forceinline__ size_t field(int pair) { return (size_t)pair * NN * N
 
 constexpr int kCtlStride = 64;  // words between two work counts of the persistent loop (ctl)
 
+// The forcing rows F0 hold each thread's 16 nodes (m, r + 16 q), q = 0..15, contiguously at
+// [row][16 r + q], so that a thread loads them as eight 16-byte words; the node codes are packed
+// per thread as well: codes[16 m + r] holds the 4-bit code of node (m, r + 16 q) in bits 4q..4q+3.
+__device__ __forceinline__ void load_forcing(const float2 *row, int r, float2 (&f)[R]) {
+  const float4 *p = reinterpret_cast<const float4 *>(row + R * r);
+#pragma unroll
+  for (int h = 0; h < R / 2; ++h) {
+    const float4 v = p[h];
+    f[2 * h] = make_float2(v.x, v.y);
+    f[2 * h + 1] = make_float2(v.z, v.w);
+  }
+}
+__device__ __forceinline__ uint32_t node_code(uint64_t w, int q) { return uint32_t(w >> (4 * q)) & 15u; }
+
 __device__ __forceinline__ void load_tw(float2 *tw, const float2 *g, int t) {
-  tw[t] = g[t];  // 256 entries, 256 threads
+  stage_tw_rk(tw, g, t, THREADS);  // (256-thread workgroups)
 }
 
 // in-pupil test of cell (cm, cn) (indices mod N)
@@ -130,7 +144,7 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   __shared__ float2 ph[(R + 2) * NN];
   static_assert(R * LP <= (R + 2) * NN, "line buffer must fit in the phi rows");
   float2 *const L = ph;
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   __shared__ uint32_t badw;  // mode 0: the block's non-finite bits
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int mode = mode_arg == 2 && int(blockIdx.x) >= nw ? 3 : mode_arg;  // uniform per block
@@ -152,14 +166,10 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
   // the forcing and the node codes of this thread's nodes, loaded with the phi rows (from
   // a valid row on the lines outside the window, whose result is replaced by zero)
   float2 f0v[R];
-  uint32_t cv[R];
+  uint64_t cw = 0;
   if (mode == 1 || mode == 2) {
-    const size_t fr = (size_t)(win_row ? m - a.o : 0) * NN;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      f0v[q] = F0[fr + r + R * q];
-      cv[q] = a.codes[m * NN + r + R * q];
-    }
+    load_forcing(F0 + (size_t)(win_row ? m - a.o : 0) * NN, r, f0v);
+    cw = a.codes[m * R + r];
   }
   __syncthreads();
   float2 fq[R];
@@ -176,11 +186,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
         if (in_pupil(a.mask, a.n, a.o, up, nl)) { measured(a, pair, up, nl, sx, sy); f = cadd(f, cadd(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, m, nl)) { measured(a, pair, m, nl, sx, sy); f = cadd(f, csub(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
-        F0[(size_t)(m - a.o) * NN + nn] = f;
+        F0[(size_t)(m - a.o) * NN + R * r + q] = f;
       }
     } else if (mode != 3) {
       f = f0v[q];
-      const uint32_t c = cv[q];
+      const uint32_t c = node_code(cw, q);
       const float2 p0 = ph[(rl + 1) * NN + nn];
       const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
       const float2 d1 = ph[(rl + 2) * NN + np], d2 = ph[rl * NN + nm];
@@ -339,7 +349,7 @@ __device__ __forceinline__ void col_tile(const MPArgs &a, float2 *L, const float
     for (int c_ = 0; c_ < NL; ++c_) {
       const int row = (t + c_ * CT) / R, cc = (t + c_ * CT) % R;
       const bool in = (row >= rlo && row <= rhi) || (border && (row == 0 || row == NN - 1));
-      v[c_] = ld2<COH>(Sin + (size_t)(in ? row : rlo) * NN + c0 + cc);
+      v[c_] = ld2<COH>(Sin + uint32_t((in ? row : rlo) * NN + c0 + cc));  // (unsigned: no sign extension)
     }
 #pragma unroll
     for (int c_ = 0; c_ < NL; ++c_) asm volatile("" : "+v"(v[c_].x), "+v"(v[c_].y));
@@ -362,7 +372,7 @@ __device__ __forceinline__ void col_tile(const MPArgs &a, float2 *L, const float
   }
   __syncthreads();
   if (act) {
-    const float *hc = h + (size_t)(c0 + cl) * NN;
+    const float *hc = h + uint32_t((c0 + cl) * NN);
 #pragma unroll
     for (int i = 0; i < NN / TPL; ++i) {
       const int p = u + TPL * i;
@@ -387,7 +397,7 @@ __device__ __forceinline__ void col_tile(const MPArgs &a, float2 *L, const float
     for (int c_ = 0; c_ < R * NN / CT; ++c_) {  // (constant trip count: unrolled, loads batched)
       const int i = t + c_ * CT;
       const int row = i / R, cc = i % R;
-      if (row >= wlo && row <= whi) st2<COH>(S + (size_t)row * NN + c0 + cc, L[cc * LP + pad(row)]);
+      if (row >= wlo && row <= whi) st2<COH>(S + uint32_t(row * NN + c0 + cc), L[cc * LP + pad(row)]);
     }
   }
 }
@@ -397,10 +407,13 @@ __global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in
                                                       int wlo, int whi, int border) {
   static_assert(TPL == 16 || TPL == 64, "16 or 64 threads per line");
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];  // TPL = 16: W_256^e; TPL = 64: the lane-ordered stage-A twiddles
+  __shared__ float2 tw[TW_RK];  // TPL = 16: tw_rk_entry; TPL = 64: the lane-ordered stage-A twiddles
   __shared__ float2 tw16[16];
   const int t = threadIdx.x;
-  if (t < NN) tw[t] = TPL == 16 ? a.tw256[t] : twq_entry(a.tw256, t);
+  if (TPL == 16)
+    stage_tw_rk(tw, a.tw256, t, R * TPL);
+  else if (t < NN)
+    tw[t] = twq_entry(a.tw256, t);
   if (TPL == 64 && t < 16) tw16[t] = tw16_entry(a.tw256, t);
   col_tile<TPL, false>(a, L, tw, tw16, t, blockIdx.y, blockIdx.x * R, in, h, rlo, rhi, wlo, whi, border);
 }
@@ -408,7 +421,7 @@ __global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in
 // ---------------------------------------------------------------- inverse rows
 __global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
   load_tw(tw, a.tw256, t);
@@ -450,20 +463,13 @@ __device__ __forceinline__ void row_inv_fwd_block(const MPArgs &a, float2 *L, co
   for (int c_ = 0; c_ < NL; ++c_) {  // (constant trip count: unrolled, loads batched)
     const int i = t + c_ * FT;
     const int row = i / NN, p = i % NN;
-    v[c_] = ld2<COH>(S + (size_t)((m0 - 1 + row) & (NN - 1)) * NN + p);
+    v[c_] = ld2<COH>(S + uint32_t(((m0 - 1 + row) & (NN - 1)) * NN + p));
   }
   const bool win_row = own && m >= a.o && m <= a.o + a.n;
   const float2 *F0 = a.f0 + (size_t)pair * (a.n + 1) * NN;
   float2 f0v[R];
-  uint32_t cv[R];
-  {
-    const size_t fr = (size_t)(win_row ? m - a.o : 0) * NN;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      f0v[q] = F0[fr + r + R * q];
-      cv[q] = a.codes[m * NN + r + R * q];
-    }
-  }
+  load_forcing(F0 + (size_t)(win_row ? m - a.o : 0) * NN, r, f0v);
+  const uint64_t cw = a.codes[m * R + r];
 #pragma unroll
   for (int c_ = 0; c_ < NL; ++c_) {
     const int i = t + c_ * FT;
@@ -481,7 +487,7 @@ __device__ __forceinline__ void row_inv_fwd_block(const MPArgs &a, float2 *L, co
   for (int q = 0; q < R; ++q) {
     const int nn = r + R * q;
     float2 f = f0v[q];
-    const uint32_t c = cv[q];
+    const uint32_t c = node_code(cw, q);
     const int np = (nn + 1) & (NN - 1), nm = (nn - 1) & (NN - 1);
     const float2 p0 = L[(sl + 1) * LP + pad(nn)];
     const float2 d1 = L[(sl + 2) * LP + pad(np)], d2 = L[sl * LP + pad(nm)];
@@ -504,7 +510,7 @@ __device__ __forceinline__ void row_inv_fwd_block(const MPArgs &a, float2 *L, co
   if (t < NN) {
     float2 *D = out + field(pair);
 #pragma unroll
-    for (int row = 0; row < R; ++row) st2<COH>(D + (size_t)(m0 + row) * NN + t, L[row * LP + pad(t)]);
+    for (int row = 0; row < R; ++row) st2<COH>(D + uint32_t((m0 + row) * NN + t), L[row * LP + pad(t)]);
   }
 }
 
@@ -514,9 +520,9 @@ __device__ __forceinline__ void row_inv_fwd_block(const MPArgs &a, float2 *L, co
 // The blocks' halo rows overlap, so the result goes to `out`, not back to a.spec.
 __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, int b0) {
   __shared__ float2 L[(R + 2) * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   const int t = threadIdx.x;
-  if (t < NN) load_tw(tw, a.tw256, t);
+  stage_tw_rk(tw, a.tw256, t, FT);
   row_inv_fwd_block<false>(a, L, tw, t, blockIdx.y, (blockIdx.x + b0) * R, out);
 }
 
@@ -542,15 +548,38 @@ struct LoopArgs {
 
 
 
-__global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  // (4 waves per SIMD: 3 workgroups per CU, as the LDS allows)
-  __shared__ float2 L[(R + 2) * LP];
-  __shared__ float2 tw[NN];
+// item -> (column tile or row block, step k, pair, tile / block index)
+struct LoopItem {
+  bool col;
+  int k, pair, sub;
+};
+// phase-major: the items of step k (every pair's column tiles, then every pair's row blocks) before
+// those of step k + 1 (an order that lags the row blocks half a step behind the column tiles, so
+// that every wait has the same slack, was measured slower: 0.753 against 0.727 ms per 128 frames)
+__device__ __forceinline__ LoopItem loop_item(int item, const LoopArgs &l) {
+  const int per = R + l.nr;
+  const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
+  const int nc = l.pairs * R;
+  LoopItem it;
+  it.col = rem < nc;
+  it.k = k;
+  it.pair = it.col ? rem / R : (rem - nc) / l.nr;
+  it.sub = it.col ? rem % R : (rem - nc) % l.nr;
+  return it;
+}
+
+// (4 waves per SIMD: 3 workgroups per CU, as the LDS allows; letting the compiler use more registers
+// instead, without spills, left one workgroup per CU by the occupancy query: 1.11 ms per 128 frames)
+__global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {
+  // one array, the twiddles first: their reads (base 16 r, offsets k) then fit the immediate offset
+  // fields of the LDS instructions, with no address register per offset
+  __shared__ float2 lds[TW_RK + (R + 2) * LP];
+  float2 *const tw = lds, *const L = lds + TW_RK;
   __shared__ int s_item;
   const int t = threadIdx.x;
-  if (t < NN) load_tw(tw, a.tw256, t);
-  const int per = R + l.nr;                          // items of one pair in one loop step (C + RF)
-  const int nc = l.pairs * R;                        // C items of a step (16 tiles per pair)
-  const int total = (a.n_iter - 1) * l.pairs * per + nc;
+  stage_tw_rk(tw, a.tw256, t, FT);
+  const int per = R + l.nr;  // items of one pair in one loop step (column tiles + row blocks)
+  const int total = (a.n_iter - 1) * l.pairs * per + l.pairs * R;
   uint32_t *next = l.ctl, *err = l.ctl + 1, *done = l.ctl + kCtlStride;
   int nxt = 0;
   if (t == 0) nxt = int(atomicAdd(next, 1u));
@@ -559,9 +588,9 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  //
       int item = nxt;
       if (item < total) {
         nxt = int(atomicAdd(next, 1u));  // (the next item is taken while this one runs)
-        const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
-        const int pair = rem < nc ? rem / R : (rem - nc) / l.nr;
-        const uint32_t need = uint32_t(k * per + (rem < nc ? 0 : R));
+        const LoopItem w = loop_item(item, l);
+        const int pair = w.pair;
+        const uint32_t need = uint32_t(w.k * per + (w.col ? 0 : R));
         int spin = 0;
         while (__hip_atomic_load(done + kCtlStride * pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           if (((++spin & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ||
@@ -582,16 +611,15 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {  //
     // out of the item loop and held in registers across it)
     int tl = t;
     asm volatile("" : "+v"(tl));
-    const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
-    int pair;
-    if (rem < nc) {
-      pair = rem / R;
-      const bool last = k == a.n_iter - 1;
-      col_tile<16, true>(a, L, tw, nullptr, tl, pair, (rem % R) * R, k == 0 ? a.spec : a.sy, a.h_loop, l.wlo,
+    __builtin_assume(tl >= 0 && tl < FT);  // (its range, which the laundering hides)
+    const LoopItem w = loop_item(item, l);
+    const int pair = w.pair;
+    if (w.col) {
+      const bool last = w.k == a.n_iter - 1;
+      col_tile<16, true>(a, L, tw, nullptr, tl, pair, w.sub * R, w.k == 0 ? a.spec : a.sy, a.h_loop, l.wlo,
                          l.whi, last ? l.last_wlo : l.rlo, last ? l.last_whi : l.rhi, 0);
     } else {
-      pair = (rem - nc) / l.nr;
-      row_inv_fwd_block<true>(a, L, tw, tl, pair, (l.wb0 + (rem - nc) % l.nr) * R, a.sy);
+      row_inv_fwd_block<true>(a, L, tw, tl, pair, (l.wb0 + w.sub) * R, a.sy);
     }
     // every store of the item is complete (seen at agent scope) before the pair's count moves
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -692,7 +720,7 @@ __global__ __launch_bounds__(THREADS) void ext_out_kernel(MPArgs a) {
 // q2 = -p(m,n) + p(m-1,n-1) + r(m,n-1) - r(m-1,n), p = s_x + s_y, r = s_x - s_y; row FFT
 __global__ __launch_bounds__(THREADS) void scatter_kernel(MPArgs a) {
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, m0 = blockIdx.x * R, m = m0 + rl, up = (m - 1) & (NN - 1);
   load_tw(tw, a.tw256, t);
@@ -937,7 +965,7 @@ __global__ __launch_bounds__(THREADS) void gen_spectrum_kernel(MPArgs a, GenArgs
 // inverse column transforms only (for the generator)
 __global__ __launch_bounds__(THREADS) void col_inv_kernel(MPArgs a) {
   __shared__ float2 L[R * LP];
-  __shared__ float2 tw[NN];
+  __shared__ float2 tw[TW_RK];
   const int t = threadIdx.x, cl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, c0 = blockIdx.x * R;
   load_tw(tw, a.tw256, t);

@@ -15,7 +15,7 @@ struct MPArgs {
   float *out;            // [B][n+1][n+1] or [B][2][N][N]
   // workspace, per frame pair: four N x N complex fields, the forcing rows and the sums
   float2 *phi, *spec, *sx, *sy;
-  float2 *f0;            // [pairs][n+1][N]
+  float2 *f0;            // [pairs][n+1][N], node (m, r + 16 q) of a row at 16 r + q
   float2 *sums;          // [pairs][2N]: C_n then R_m
   uint32_t *bad;         // [pairs][N/16]: per window row block, bit 0 (frame A) and bit 1 (frame B)
                          // set where an in-pupil measured slope is not finite
@@ -23,7 +23,8 @@ struct MPArgs {
   const float *h_final;
   const float2 *tw256;   // W_256^e, e = 0..255
   const uint8_t *mask;   // [n][n]
-  const uint8_t *codes;  // [N][N]: out-of-pupil bits of the 4 cells around each node
+  const uint64_t *codes; // [N][16]: out-of-pupil bits of the 4 cells around each node, node (m, r + 16 q)
+                         // in bits 4q..4q+3 of codes[16 m + r]
   uint32_t *ctl;         // work counters of the persistent loop kernel
   const uint32_t *loop_err = nullptr;  // set by the launcher after a persistent loop: its error word
   int B, n, o, n_iter, flags;
