@@ -186,7 +186,6 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
         if (in_pupil(a.mask, a.n, a.o, up, nl)) { measured(a, pair, up, nl, sx, sy); f = cadd(f, cadd(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, m, nl)) { measured(a, pair, m, nl, sx, sy); f = cadd(f, csub(sx, sy)); }
         if (in_pupil(a.mask, a.n, a.o, up, nn)) { measured(a, pair, up, nn, sx, sy); f = csub(f, csub(sx, sy)); }
-        F0[(size_t)(m - a.o) * NN + R * r + q] = f;
       }
     } else if (mode != 3) {
       f = f0v[q];
@@ -209,6 +208,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
       }
     }
     fq[q] = f;
+  }
+  if (mode == 0 && win_row) {  // the forcing rows, each thread's 16 nodes as eight 16-byte words
+    float4 *F4 = reinterpret_cast<float4 *>(F0 + (size_t)(m - a.o) * NN + R * r);
+#pragma unroll
+    for (int h = 0; h < R / 2; ++h) F4[h] = make_float4(fq[2 * h].x, fq[2 * h].y, fq[2 * h + 1].x, fq[2 * h + 1].y);
   }
   if (mode == 3) {  // (q2 = 0 on the block's other rows)
     // C_n for n = t from the b0 <= N/16 partials (fixed order, loads issued together), staged in
