@@ -627,8 +627,12 @@ def uneven_main(args):
         "eager_ms_per_step": eager_ms,
         "config": {"workload": "2048x24^2 + 2048x40^2 (CNN start) + 512x64^2 + 64x128^2 SH frames, padded 2x, "
                                "10 iterations + Eq.5 + MMSE, fresh von Karman frames each step",
+                   # (a multi-pass item of the grouped call runs one launch per pass whatever its
+                   # tuned schedule: schedule 2's waiting workgroups would hold CUs the others need)
                    "items": [{"n_sub": n, "frames": B, "frames_per_group": p.launch_info()[1],
-                              "fft_radix_schedule": p.schedule} for (n, B, _), p in zip(UNEVEN, plans)],
+                              "fft_radix_schedule": p.schedule,
+                              **({"loop_in_group": "one launch per pass"} if 2 * n == 256 else {})}
+                             for (n, B, _), p in zip(UNEVEN, plans)],
                    "learned_start": net is not None},
     }
     for p in plans:

@@ -361,7 +361,8 @@ static fwr_status check_args(fwr_plan_t plan, const float *in, const float *out,
 // min(B, *count - count_off) are processed (see OnchipArgs).
 static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, bool extend,
                       const float *start = nullptr, float *resid = nullptr, hipStream_t stream = nullptr,
-                      bool use_stream = false, const int32_t *count = nullptr, int count_off = 0) {
+                      bool use_stream = false, const int32_t *count = nullptr, int count_off = 0,
+                      bool beside_others = false) {
   if (const fwr_status c = check_args(plan, in, out, B, extend, start, resid); c != FWR_OK) return c;
   if (B == 0) return FWR_OK;
   const hipStream_t st = use_stream ? stream : plan->stream;
@@ -392,7 +393,10 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.slopes = in;
     a.out = out;
     a.B = B;
-    a.col_shape = plan->sched;
+    // beside other items of a grouped call the loop runs one launch per pass: the persistent
+    // loop's resident workgroups wait in place and hold CUs that the concurrent items need
+    // (measured on the mixed step: 1.050 ms per step against 1.089 ms)
+    a.col_shape = beside_others && plan->sched == 2 ? 0 : plan->sched;
     return fwr::multipass_run(a, extend, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
   fwr::OnchipArgs a;
@@ -495,12 +499,14 @@ fwr_status fwr_reconstruct_group(const fwr_work *work, int32_t n_work, void *str
     }
     ++forked;
     const fwr_work &w = work[i];
-    const fwr_status r = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, st, true);
+    const fwr_status r =
+        run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, st, true, nullptr, 0, n_work > 1);
     if (r != FWR_OK && status == FWR_OK) status = r;
   }
   if (fork_ok) {
     const fwr_work &w = work[lead];
-    const fwr_status r = run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, main, true);
+    const fwr_status r =
+        run(w.plan, w.d_slopes, w.d_phase, w.B, false, w.d_start, w.d_resid, main, true, nullptr, 0, n_work > 1);
     if (r != FWR_OK && status == FWR_OK) status = r;
   }
   // every forked branch joins back into the caller's stream, also after a failed launch

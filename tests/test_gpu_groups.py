@@ -158,6 +158,32 @@ def test_grouped_call_keeps_each_plans_schedule(F):
         plan.close()
 
 
+def test_grouped_call_with_a_persistent_loop_plan(F):
+    """A multi-pass plan on schedule 2 (the persistent loop) in a grouped call: beside other items it
+    runs one launch per pass, alone in a group the persistent loop; every way gives the bits of the
+    plan's own call (the two loop shapes do the same arithmetic)."""
+    _flush("[gpu] grouped call, persistent multi-pass loop")
+    mp = F.Plan(128, 256, I.pupil_mask(128), n_iter=5, periodic=True, max_batch=6, d=39.0 / 128)
+    mp.set_schedule(2)
+    xm = torch.from_numpy(I.random_slopes(6, 128, seed=5).astype(np.float32)).cuda()
+    ref = mp.reconstruct(xm)
+    oc = F.Plan(24, 48, I.pupil_mask(24), n_iter=5, periodic=True, max_batch=4, d=8.0 / 24)
+    xo = torch.from_numpy(I.random_slopes(4, 24, seed=6).astype(np.float32)).cuda()
+    om = torch.empty_like(ref)
+    oo = torch.empty((4, 25, 25), device="cuda")
+    F.reconstruct_group([(oc, xo, oo, None, None), (mp, xm, om, None, None)])
+    torch.cuda.synchronize()
+    assert torch.equal(om, ref) and torch.equal(oo, oc.reconstruct(xo))
+    om.zero_()
+    F.reconstruct_group([(mp, xm, om, None, None)])
+    torch.cuda.synchronize()
+    assert torch.equal(om, ref)
+    mp.set_schedule(0)
+    assert torch.equal(mp.reconstruct(xm), ref)
+    mp.close()
+    oc.close()
+
+
 def test_grouped_call_mixes_slope_models_and_paths(F):
     """A group of a lenslet-averaging (sinc) plan, a Fried on-chip plan and a multi-pass plan gives
     the bits of the individual calls."""
