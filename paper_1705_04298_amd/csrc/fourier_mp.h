@@ -22,11 +22,17 @@ struct FSArgs {
   const float2 *fin_b;
   const float2 *tw256;   // W_256^e, e = 0..255
   const uint8_t *mask;   // [n][n]
+  uint32_t *ctl;         // work counters of the persistent loop: [0] next item, [1] error, one count
+                         // per frame on its own 256-byte line
+  const uint32_t *loop_err = nullptr;  // set by the launcher after a persistent loop: its error word
+  int wait_limit = 1 << 20;            // polls of a count before the persistent loop gives up
+  int shape = 0;                       // 0: one launch per pass; 2: the loop as one persistent launch
   int B, n, o, n_iter, flags;  // flags: kFourierPeriodic, kFourierPeriodicEach (fourier.h)
 };
 
 bool fourier_mp_supported(int N);
 size_t fourier_mp_workspace_bytes(int N, int max_batch);
+size_t fourier_mp_ctl_words(int max_batch);
 hipError_t fourier_mp_run(const FSArgs &a, bool extend, hipStream_t s);
 
 }  // namespace fwr

@@ -374,6 +374,7 @@ static fwr_status run(fwr_plan_t plan, const float *in, float *out, int32_t B, b
     a.B = B;
     a.flags = ((plan->flags & fwr::kFlagPeriodic) ? fwr::kFourierPeriodic : 0) |
               ((plan->flags & fwr::kFlagPeriodicEach) ? fwr::kFourierPeriodicEach : 0);
+    a.shape = beside_others ? 0 : plan->sched;  // (as on the Fried multi-pass path below)
     return fwr::fourier_mp_run(a, extend, st) == hipSuccess ? FWR_OK : FWR_E_DEVICE;
   }
   if (plan->fourier) {
@@ -742,7 +743,7 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group) {
 fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
   if (!valid(plan)) return FWR_E_STATE;
   if (schedule < 0 || schedule > 2) return FWR_E_INVAL;
-  if (schedule == 2 && !plan->multipass) return FWR_E_UNSUPPORTED;
+  if (schedule == 2 && !plan->multipass && !plan->fourier_mp) return FWR_E_UNSUPPORTED;
   if (schedule == 1 && !plan->multipass &&
       (plan->fourier || plan->fourier_mp || (plan->flags & fwr::kFlagPeriodicEach) != 0 ||
        !fwr::onchip_sched_ok(plan->N, plan->n)))
@@ -753,9 +754,10 @@ fwr_status fwr_plan_set_schedule(fwr_plan_t plan, int32_t schedule) {
 
 fwr_status fwr_plan_set_wait_limit(fwr_plan_t plan, int32_t polls) {
   if (!valid(plan)) return FWR_E_STATE;
-  if (!plan->multipass) return FWR_E_UNSUPPORTED;
+  if (!plan->multipass && !plan->fourier_mp) return FWR_E_UNSUPPORTED;
   if (polls < 1 || polls > (1 << 24)) return FWR_E_INVAL;
-  plan->mp.wait_limit = polls;
+  if (plan->multipass) plan->mp.wait_limit = polls;
+  else plan->fs.wait_limit = polls;
   return FWR_OK;
 }
 
@@ -769,15 +771,11 @@ fwr_status fwr_plan_get_schedule(fwr_plan_t plan, int32_t *schedule) {
 fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_group) {
   if (!valid(plan)) return FWR_E_STATE;
   if (B < 1 || B > plan->max_batch) return FWR_E_INVAL;
-  if (plan->fourier_mp) {
-    if (frames_per_group) *frames_per_group = 1;
-    return FWR_OK;
-  }
   const bool each = (plan->flags & fwr::kFlagPeriodicEach) != 0;
   const int n = plan->n, N = plan->N;
   // candidate launch shapes: frame pairs per workgroup (on-chip) or frames (Fourier-domain);
-  // the multi-pass path has one (a frame pair per field) and two column-pass shapes
-  const bool mp = plan->multipass;
+  // the multi-pass paths have one (a frame pair, or a frame, per field) and their loop shapes
+  const bool mp = plan->multipass || plan->fourier_mp;
   int *unit = plan->fourier ? &plan->frames : &plan->pairs;
   auto shape_ok = [&](int u) {
     if (mp) return u == 1;
@@ -800,12 +798,13 @@ fwr_status fwr_plan_autotune(fwr_plan_t plan, int32_t B, int32_t *frames_per_gro
   // multi-pass path's launch shapes (column passes of 16 or 64 threads per line, or the loop as
   // one persistent launch)
   const int n_sched = mp ? 3 : (!plan->fourier && !each && fwr::onchip_sched_ok(N, n) ? 2 : 1);
+  // (the lenslet-averaging multi-pass path has shapes 0 and 2: one launch per pass or persistent)
   int best = before, best_sched = sched_before;
   float best_ms = 0.f;
   for (int pairs : kPairsOptions) {
     for (int sc = 0; sc < n_sched; ++sc) {
       if (!ok) break;
-      if (!shape_ok(pairs)) continue;
+      if (!shape_ok(pairs) || (plan->fourier_mp && sc == 1)) continue;
       *unit = pairs;
       plan->sched = sc;
       float ms = 0.f;
@@ -1054,6 +1053,7 @@ fwr_status plan_fourier_mp(const fwr_params &p, fwr_plan_t *out) {
   a.state = reinterpret_cast<float2 *>(w + B * NNs * sizeof(float2));
   a.rsum = reinterpret_cast<float *>(w + 2 * B * NNs * sizeof(float2));
   a.cpart = a.rsum + B * N;
+  a.ctl = reinterpret_cast<uint32_t *>(a.cpart + B * (size_t)(N / 16) * N);
   a.alpha = reinterpret_cast<const float *>(mem);
   a.beta = reinterpret_cast<const float2 *>(mem + off_b);
   a.fin_a = reinterpret_cast<const float2 *>(mem + off_fa);
@@ -1076,6 +1076,8 @@ fwr_status plan_fourier_mp(const fwr_params &p, fwr_plan_t *out) {
   plan->fourier_mp = true;
   plan->dmask = a.mask;
   plan->d = p.d;
+  // the loop's launch shape autotuned earlier in the process for this shape, else one launch per pass
+  plan->sched = tuned_value(plan->device, N, n, p.n_iter, p.periodic_each_iter != 0, FWR_MODEL_SINC) / 16;
   *out = plan;
   return FWR_OK;
 }

@@ -243,16 +243,18 @@ def test_sinc_128_start_values_and_residual(F):
     plan.close()
 
 
+@pytest.mark.parametrize("schedule", [0, 2])
 @pytest.mark.parametrize("n,n_iter,periodic,each,dpx", [(128, 20, True, False, 0.0), (128, 5, False, False, 0.0),
                                                        (128, 3, True, True, 0.0), (128, 0, True, False, 0.0),
                                                        (128, 6, True, False, 1.0 / 6.0), (254, 4, True, False, 0.0)])
-def test_sinc_256_multipass_matches_oracle(F, n, n_iter, periodic, each, dpx):
+def test_sinc_256_multipass_matches_oracle(F, n, n_iter, periodic, each, dpx, schedule):
     """The lenslet-averaging model on the 256 x 256 grid (multi-pass through HBM): phase and
     extended slopes against the oracle (measured slopes bit for bit), ELT frames measured with the
     model (D = 39 m), with and without Eq. 5, per-iteration Eq. 5, zero iterations, the d - d_px
-    correction, and a one-cell border (n = 254)."""
+    correction, and a one-cell border (n = 254); the loop as one launch per pass (schedule 0) and
+    as one persistent launch (schedule 2)."""
     import dataclasses
-    _flush(f"[gpu] sinc 256 n={n} it={n_iter} periodic={periodic} each={each} dpx={dpx:.3f}")
+    _flush(f"[gpu] sinc 256 n={n} it={n_iter} periodic={periodic} each={each} dpx={dpx:.3f} sched={schedule}")
     N, B = 256, 3
     if n == 128:
         w = dataclasses.replace(I.ELT_128, model="sinc", d_px_frac=dpx, config_id=7)
@@ -265,6 +267,7 @@ def test_sinc_256_multipass_matches_oracle(F, n, n_iter, periodic, each, dpx):
     p = O.Params(n_sub=n, n_grid=N, n_iter=n_iter, periodic=periodic, periodic_each_iter=each, d=d,
                  d_px=dpx * d, model="sinc")
     plan = _plan(F, p, mask, B)
+    plan.set_schedule(schedule)
     x = torch.from_numpy(slopes).cuda()
     got = plan.reconstruct(x).cpu().numpy().astype(np.float64)
     ext = plan.extend(x).cpu().numpy().astype(np.float64) if n_iter > 0 else None
@@ -280,6 +283,52 @@ def test_sinc_256_multipass_matches_oracle(F, n, n_iter, periodic, each, dpx):
             assert np.abs(ext[b, 1] - ref.sy).max() <= 1e-4 * scale
             assert np.array_equal(ext[b, 0, o:o + n, o:o + n][m], slopes[b, 0][m].astype(np.float64))
             assert np.array_equal(ext[b, 1, o:o + n, o:o + n][m], slopes[b, 1][m].astype(np.float64))
+    plan.close()
+
+
+@pytest.mark.parametrize("B,n_iter,periodic", [(5, 20, True), (7, 2, True), (4, 3, False), (64, 10, True)])
+def test_sinc_256_persistent_loop_same_bits(F, B, n_iter, periodic):
+    """The persistent loop (schedule 2) runs the column-block and row-step arithmetic of the
+    launch-per-pass loop: bit-identical phases and extended slopes."""
+    import dataclasses
+    _flush(f"[gpu] sinc 256 persistent vs per pass B={B} n_iter={n_iter} periodic={periodic}")
+    w = dataclasses.replace(I.ELT_128, model="sinc", config_id=8)
+    x = torch.from_numpy(I.make_batch(w, B, dtype=np.float32)).cuda()
+    p = O.Params(n_sub=128, n_grid=256, n_iter=n_iter, periodic=periodic, d=39.0 / 128, model="sinc")
+    plan = _plan(F, p, I.pupil_mask(128), B)
+    res = {}
+    for sc in (0, 2):
+        plan.set_schedule(sc)
+        res[sc] = (plan.reconstruct(x), plan.extend(x))
+    assert torch.isfinite(res[2][0]).all()
+    assert torch.equal(res[0][0], res[2][0]) and torch.equal(res[0][1], res[2][1])
+    plan.close()
+
+
+def test_sinc_256_persistent_loop_watchdog(F):
+    """A one-poll wait limit makes the persistent loop give up (forced from the host): every frame
+    NaN or every frame exact, and the next call with the default limit exact."""
+    import dataclasses
+    _flush("[gpu] sinc 256 persistent loop watchdog")
+    B = 128
+    w = dataclasses.replace(I.ELT_128, model="sinc", config_id=9)
+    base = I.make_batch(w, 8, dtype=np.float32)
+    x = torch.from_numpy(np.ascontiguousarray(np.concatenate([base] * (B // 8)))).cuda()
+    p = O.Params(n_sub=128, n_grid=256, n_iter=10, periodic=True, d=39.0 / 128, model="sinc")
+    plan = _plan(F, p, I.pupil_mask(128), B)
+    ref = plan.reconstruct(x).cpu().numpy()
+    plan.set_schedule(2)
+    plan.set_wait_limit(1)
+    gave_up = 0
+    for _ in range(3):
+        got = plan.reconstruct(x).cpu().numpy()
+        if np.isnan(got).all():
+            gave_up += 1
+        else:
+            assert np.array_equal(got, ref)
+    assert gave_up > 0
+    plan.set_wait_limit(1 << 20)
+    assert np.array_equal(plan.reconstruct(x).cpu().numpy(), ref)
     plan.close()
 
 
