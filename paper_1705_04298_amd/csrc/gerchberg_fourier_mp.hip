@@ -14,6 +14,8 @@
 //          16 a + b is 16 (16 - a) + 15 - b (a > 0) or (16 - b) mod 16 (a = 0): position groups
 //          a and 16 - a pair up, groups 0 and 8 are closed.  A block takes 8 contiguous
 //          positions of group a and their 8 (contiguous) mirrors, or all of group 0 or 8.
+// With launch shape 2 the loop's column passes and row steps run as one persistent launch
+// (loop_kernel, below).
 #include <algorithm>
 
 #include "fft256.h"

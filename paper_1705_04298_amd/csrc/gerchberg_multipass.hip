@@ -12,7 +12,9 @@
 //   row_inv_fwd : between two solves of the pruned loop, row_inv and the next row_fwd in
 //                 one pass (phi stays in LDS)  -> second spectrum field, read by col
 // and, once per call, the explicit final step (cell slopes, Eq. 5 sums and
-// fix, scatter to q) and the output kernels.
+// fix, scatter to q) and the output kernels.  With launch shape 2 the loop's col
+// and row_inv_fwd steps run as one persistent launch (loop_kernel, below) whose
+// workgroups hand the spectra to one another.
 //
 // Without per-iteration Eq. 5 the loop is pruned to the window, as in the on-chip
 // kernel: q2 vanishes outside the n+1 window rows (it is G^T of slopes that differ from
