@@ -17,6 +17,7 @@
 // With launch shape 2 the loop's column passes and row steps run as one persistent launch
 // (loop_kernel, below).
 #include <algorithm>
+#include <atomic>
 
 #include "fft256.h"
 #include "fourier.h"
@@ -395,17 +396,17 @@ size_t fourier_mp_ctl_words(int max_batch) { return (size_t)fs::kCtl * ((size_t)
 
 // resident workgroups of the persistent loop kernel on the current device (occupancy x CUs)
 static int fs_loop_grid() {
-  static int grid[64] = {};
+  static std::atomic<int> grid[64] = {};  // (per device; concurrent first calls store the same value)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (grid[dev] == 0) {
+  if (grid[dev].load() == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fs::loop_kernel, mp::THREADS, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    grid[dev] = (per_cu > 0 ? per_cu : 1) * cus;
+    grid[dev].store((per_cu > 0 ? per_cu : 1) * cus);
   }
-  return grid[dev];
+  return grid[dev].load();
 }
 
 hipError_t fourier_mp_run(const FSArgs &a0, bool extend, hipStream_t s) {

@@ -32,6 +32,7 @@
 // table is laid out in that order and the inverse undoes it.  Lines are
 // padded by one element every 16, plus one (273 per line), to spread LDS banks.
 #include <algorithm>
+#include <atomic>
 
 #include "fft256.h"
 #include "multipass.h"
@@ -783,17 +784,17 @@ size_t multipass_ctl_words(int max_batch) { return mp::kCtlStride * ((size_t)(ma
 
 // resident workgroups of the persistent loop kernel on the current device (occupancy x CUs)
 static int loop_grid() {
-  static int grid[64] = {};
+  static std::atomic<int> grid[64] = {};  // (per device; concurrent first calls store the same value)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (grid[dev] == 0) {
+  if (grid[dev].load() == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mp::loop_kernel, mp::FT, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    grid[dev] = (per_cu > 0 ? per_cu : 1) * cus;
+    grid[dev].store((per_cu > 0 ? per_cu : 1) * cus);
   }
-  return grid[dev];
+  return grid[dev].load();
 }
 
 bool multipass_supported(int N) { return N == mp::NN; }
