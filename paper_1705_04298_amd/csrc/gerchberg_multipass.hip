@@ -426,31 +426,68 @@ __global__ __launch_bounds__(R * TPL) void col_kernel(MPArgs a, const float2 *in
 }
 
 // ---------------------------------------------------------------- inverse rows
-__global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0) {
+// Inverse row FFTs of 16 spectrum rows m0 .. m0+15 of a pair (the body of row_inv_kernel; the
+// persistent loop runs it with COH for the loop's last solve, its threads past the first 256
+// idle): phi rows, or with to_out the (n+1) x (n+1) node window of phi as the pair's two phase
+// frames (NaN for a flagged frame).
+template <bool COH>
+__device__ __forceinline__ void row_inv_block(const MPArgs &a, float2 *L, const float2 *tw, int t, int pair, int m0,
+                                              bool to_out) {
+  const int rl = t >> 4, r = t & 15;
+  const bool act = t < THREADS;
+  const float2 *S = a.spec + field(pair);
+  constexpr int NL = R * NN / THREADS;
+  if (act) {
+    float2 v[NL];
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) {  // (constant trip count: unrolled, loads batched)
+      const int i = t + c_ * THREADS;
+      v[c_] = ld2<COH>(S + uint32_t((m0 + i / NN) * NN + i % NN));
+    }
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) {
+      const int i = t + c_ * THREADS;
+      L[(i / NN) * LP + pad(i % NN)] = v[c_];
+    }
+  }
+  __syncthreads();
+  if (act) fft_stage_b<+1>(L + rl * LP, r);
+  __syncthreads();
+  if (act) fft_stage_a<+1>(L + rl * LP, r, tw);
+  __syncthreads();
+  if (!act) return;
+  if (!to_out) {
+    float2 *Ph = a.phi + field(pair);
+#pragma unroll
+    for (int c_ = 0; c_ < NL; ++c_) {
+      const int i = t + c_ * THREADS;
+      const int row = i / NN, p = i % NN;
+      Ph[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
+    }
+    return;
+  }
+  const int n1 = a.n + 1;
+  float *oa = a.out + (size_t)(2 * pair) * n1 * n1;
+  const bool hasB = 2 * pair + 1 < a.B;
+  const uint32_t bad = pair_bad(a, pair);
+#pragma unroll
+  for (int c_ = 0; c_ < NL; ++c_) {
+    const int i = t + c_ * THREADS;
+    const int m = m0 + i / NN, p = i % NN;
+    if (m < a.o || m > a.o + a.n || p < a.o || p > a.o + a.n) continue;
+    const float2 w = L[(i / NN) * LP + pad(p)];
+    const size_t idx = (size_t)(m - a.o) * n1 + (p - a.o);
+    oa[idx] = bad & 1u ? nan_f() : w.x;
+    if (hasB) oa[(size_t)n1 * n1 + idx] = bad & 2u ? nan_f() : w.y;
+  }
+}
+
+__global__ __launch_bounds__(THREADS) void row_inv_kernel(MPArgs a, int b0, int to_out) {
   __shared__ float2 L[R * LP];
   __shared__ float2 tw[TW_RK];
-  const int t = threadIdx.x, rl = t >> 4, r = t & 15;
-  const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R;
+  const int t = threadIdx.x;
   load_tw(tw, a.tw256, t);
-  const float2 *S = a.spec + field(pair);
-#pragma unroll
-  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
-    const int i = t + c_ * THREADS;
-    const int row = i / NN, p = i % NN;
-    L[row * LP + pad(p)] = S[(size_t)(m0 + row) * NN + p];
-  }
-  __syncthreads();
-  fft_stage_b<+1>(L + rl * LP, r);
-  __syncthreads();
-  fft_stage_a<+1>(L + rl * LP, r, tw);
-  __syncthreads();
-  float2 *Ph = a.phi + field(pair);
-#pragma unroll
-  for (int c_ = 0; c_ < R * NN / THREADS; ++c_) {  // (constant trip count: unrolled, loads batched)
-    const int i = t + c_ * THREADS;
-    const int row = i / NN, p = i % NN;
-    Ph[(size_t)(m0 + row) * NN + p] = L[row * LP + pad(p)];
-  }
+  row_inv_block<false>(a, L, tw, t, blockIdx.y, (blockIdx.x + b0) * R, to_out != 0);
 }
 
 // ---------------------------------------------------------------- inverse rows + next forward rows
@@ -534,16 +571,16 @@ __global__ __launch_bounds__(FT) void row_inv_fwd_kernel(MPArgs a, float2 *out, 
 }
 
 // ---------------------------------------------------------------- persistent loop
-// The pruned loop's column passes and fused row steps, C_0, RF_0, C_1, ..., RF_{K-2}, C_{K-1}
-// (K = n_iter), as one launch of resident workgroups that take work items in that order from a
-// counter: item = (step, pair, 16-column tile or window row block).  An item waits until every
-// item of its pair in the previous step is done (a per-pair count), so pairs move through the
-// steps independently and one pair's loads overlap another's transforms, without a grid-wide
-// barrier between the steps.  Items are taken in order and wait only on earlier items, taken by
-// workgroups that are running, so the launch cannot deadlock whatever the number of resident
-// workgroups.  A wait longer than a.wait_limit polls (~1 us each; default 2^20) sets the error
-// word; every workgroup then stops, and the frames are written as NaN (pair_bad).  The counters are zeroed by
-// the start pass (row_fwd_kernel, mode 0) before the launch.
+// The pruned loop's column passes and fused row steps, C_0, RF_0, C_1, ..., RF_{K-2}, C_{K-1},
+// then the last solve's inverse row FFTs (K = n_iter), as one launch of resident workgroups that
+// take work items in that order from a counter: item = (step, pair, 16-column tile or row
+// block).  An item waits until every item of its pair in the previous step is done (a per-pair
+// count), so pairs move through the steps independently and one pair's loads overlap another's
+// transforms, without a grid-wide barrier between the steps.  Items are taken in order and wait
+// only on earlier items, taken by workgroups that are running, so the launch cannot deadlock
+// whatever the number of resident workgroups.  A wait longer than a.wait_limit polls (~1 us each;
+// default 2^20) sets the error word; every workgroup then stops, and the frames are written as
+// NaN (pair_bad).  The counters are zeroed by the start pass (row_fwd_kernel, mode 0).
 struct LoopArgs {
   uint32_t *ctl;          // [0] next item, [1] error, [64 (pair + 1)] items of the pair done (one
                           // 256-byte line per count: the waiting workgroups poll them)
@@ -551,27 +588,36 @@ struct LoopArgs {
   int wlo, whi;           // rows the column passes read (the window rows)
   int rlo, rhi;           // rows they write back (the stencil's reach)
   int last_wlo, last_whi; // rows the last column pass writes back
+  int ri_b0, nri;         // row blocks of the last solve's inverse row FFTs (phi)
 };
 
 
 
-// item -> (column tile or row block, step k, pair, tile / block index)
+// item -> (column tile, fused row block or last-solve row block; step k, pair, tile / block index)
 struct LoopItem {
-  bool col;
+  int kind;  // 0 column tile, 1 fused row step block, 2 the last solve's inverse row block
   int k, pair, sub;
 };
 // phase-major: the items of step k (every pair's column tiles, then every pair's row blocks) before
 // those of step k + 1 (an order that lags the row blocks half a step behind the column tiles, so
 // that every wait has the same slack, was measured slower: 0.753 against 0.727 ms per 128 frames)
-__device__ __forceinline__ LoopItem loop_item(int item, const LoopArgs &l) {
+__device__ __forceinline__ LoopItem loop_item(int item, const LoopArgs &l, int n_iter) {
   const int per = R + l.nr;
+  const int ri0 = (n_iter - 1) * l.pairs * per + l.pairs * R;  // the last solve's items follow the last C step
+  LoopItem it;
+  if (item >= ri0) {
+    it.kind = 2;
+    it.k = n_iter - 1;
+    it.pair = (item - ri0) / l.nri;
+    it.sub = (item - ri0) % l.nri;
+    return it;
+  }
   const int k = item / (l.pairs * per), rem = item % (l.pairs * per);
   const int nc = l.pairs * R;
-  LoopItem it;
-  it.col = rem < nc;
+  it.kind = rem < nc ? 0 : 1;
   it.k = k;
-  it.pair = it.col ? rem / R : (rem - nc) / l.nr;
-  it.sub = it.col ? rem % R : (rem - nc) % l.nr;
+  it.pair = rem < nc ? rem / R : (rem - nc) / l.nr;
+  it.sub = rem < nc ? rem % R : (rem - nc) % l.nr;
   return it;
 }
 
@@ -586,7 +632,7 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {
   const int t = threadIdx.x;
   stage_tw_rk(tw, a.tw256, t, FT);
   const int per = R + l.nr;  // items of one pair in one loop step (column tiles + row blocks)
-  const int total = (a.n_iter - 1) * l.pairs * per + l.pairs * R;
+  const int total = (a.n_iter - 1) * l.pairs * per + l.pairs * (R + l.nri);
   uint32_t *next = l.ctl, *err = l.ctl + 1, *done = l.ctl + kCtlStride;
   int nxt = 0;
   if (t == 0) nxt = int(atomicAdd(next, 1u));
@@ -595,9 +641,9 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {
       int item = nxt;
       if (item < total) {
         nxt = int(atomicAdd(next, 1u));  // (the next item is taken while this one runs)
-        const LoopItem w = loop_item(item, l);
+        const LoopItem w = loop_item(item, l, a.n_iter);
         const int pair = w.pair;
-        const uint32_t need = uint32_t(w.k * per + (w.col ? 0 : R));
+        const uint32_t need = uint32_t(w.k * per + (w.kind == 0 ? 0 : R));
         int spin = 0;
         while (__hip_atomic_load(done + kCtlStride * pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           if (((++spin & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ||
@@ -619,14 +665,16 @@ __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {
     int tl = t;
     asm volatile("" : "+v"(tl));
     __builtin_assume(tl >= 0 && tl < FT);  // (its range, which the laundering hides)
-    const LoopItem w = loop_item(item, l);
+    const LoopItem w = loop_item(item, l, a.n_iter);
     const int pair = w.pair;
-    if (w.col) {
+    if (w.kind == 0) {
       const bool last = w.k == a.n_iter - 1;
       col_tile<16, true>(a, L, tw, nullptr, tl, pair, w.sub * R, w.k == 0 ? a.spec : a.sy, a.h_loop, l.wlo,
                          l.whi, last ? l.last_wlo : l.rlo, last ? l.last_whi : l.rhi, 0);
-    } else {
+    } else if (w.kind == 1) {
       row_inv_fwd_block<true>(a, L, tw, tl, pair, (l.wb0 + w.sub) * R, a.sy);
+    } else {
+      row_inv_block<true>(a, L, tw, tl, pair, (l.ri_b0 + w.sub) * R, false);
     }
     // every store of the item is complete (seen at agent scope) before the pair's count moves
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -754,21 +802,6 @@ __global__ __launch_bounds__(THREADS) void scatter_kernel(MPArgs a) {
   }
 }
 
-// (n+1) x (n+1) node window of phi
-__global__ __launch_bounds__(THREADS) void phase_out_kernel(MPArgs a) {
-  const int pair = blockIdx.y, i = blockIdx.x;  // window row
-  const int n1 = a.n + 1;
-  const float2 *P = a.phi + field(pair);
-  float *oa = a.out + (size_t)(2 * pair) * n1 * n1;
-  const bool hasB = 2 * pair + 1 < a.B;
-  const uint32_t bad = pair_bad(a, pair);
-  for (int j = threadIdx.x; j < n1; j += THREADS) {
-    const float2 v = P[(size_t)(a.o + i) * NN + a.o + j];
-    oa[(size_t)i * n1 + j] = bad & 1u ? nan_f() : v.x;
-    if (hasB) oa[(size_t)n1 * n1 + (size_t)i * n1 + j] = bad & 2u ? nan_f() : v.y;
-  }
-}
-
 }  // namespace mp
 
 size_t multipass_workspace_bytes(int N, int n, int max_batch) {
@@ -850,15 +883,13 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     l.rhi = rhi;
     l.last_wlo = full_last ? 0 : rlo;
     l.last_whi = full_last ? NN - 1 : rhi;
+    l.ri_b0 = full_last ? 0 : rb0;  // the loop's last solve: inverse row FFTs of these row blocks
+    l.nri = full_last ? NN / R : rb1 - rb0 + 1;
     const long total = (long)(a.n_iter - 1) * pairs * (R + l.nr) + (long)pairs * R;
     // resident workgroups, at most half the items of one loop step (more only wait: measured)
     const long cap = std::min<long>(lgrid, (long)pairs * (R + l.nr) / 2);
     hipLaunchKernelGGL(loop_kernel, dim3((unsigned)std::max<long>(cap, 1)), dim3(FT), 0, s, a, l);
     a.loop_err = a.ctl + 1;  // read by the output kernels (pair_bad)
-    if (full_last)
-      hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
-    else
-      hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0);
   }
   for (int it = 0; it < (lgrid > 0 ? 0 : a.n_iter); ++it) {
     const bool last = it == a.n_iter - 1;
@@ -874,9 +905,9 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
       continue;
     }
     if (full_out)
-      hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
+      hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0, 0);
     else
-      hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0);
+      hipLaunchKernelGGL(row_inv_kernel, rrows, blk, 0, s, a, rb0, 0);
     if (last) break;
     explicit_q(false, true);  // per-iteration Eq. 5
     hipLaunchKernelGGL(scatter_kernel, rows, blk, 0, s, a);
@@ -902,8 +933,7 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   // the output is the window rows
   col(a.spec, a.h_final, win_final ? wlo : 0, win_final ? whi : NN - 1, wlo,
                      whi, border ? 1 : 0);
-  hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0);
-  hipLaunchKernelGGL(phase_out_kernel, dim3(a.n + 1, pairs), blk, 0, s, a);
+  hipLaunchKernelGGL(row_inv_kernel, wrows, blk, 0, s, a, wb0, 1);  // (phi's window rows straight to the output)
   return hipGetLastError();
 }
 
@@ -1045,7 +1075,7 @@ hipError_t multipass_generate(const MPArgs &a, const GenArgs &g, hipStream_t s) 
   const dim3 rows(NN / R, pairs), blk(THREADS);
   hipLaunchKernelGGL(gen_spectrum_kernel, rows, blk, 0, s, a, g);
   hipLaunchKernelGGL(col_inv_kernel, rows, blk, 0, s, a);
-  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0);
+  hipLaunchKernelGGL(row_inv_kernel, rows, blk, 0, s, a, 0, 0);
   hipLaunchKernelGGL(gen_slopes_kernel, dim3(16, pairs), blk, 0, s, a, g);
   if (g.d_counter) hipLaunchKernelGGL(mp_counter_add_kernel, dim3(1), dim3(64), 0, s, g.d_counter, uint64_t(2 * pairs));
   return hipGetLastError();
