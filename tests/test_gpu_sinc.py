@@ -332,13 +332,41 @@ def test_sinc_256_persistent_loop_watchdog(F):
     plan.close()
 
 
-def test_sinc_256_in_a_grouped_call(F):
+def test_sinc_256_autotune_picks_a_loop_shape(F):
+    """The autotuner times the two loop shapes of the lenslet-averaging multi-pass plan (one launch
+    per pass, persistent), keeps the faster, and later plans of the shape start from it; the chosen
+    shape stays within the oracle's tolerance."""
+    _flush("[gpu] sinc 256 autotune")
+    p = O.Params(n_sub=128, n_grid=256, n_iter=4, periodic=True, d=39.0 / 128, model="sinc")
+    mask = I.pupil_mask(128)
+    plan = _plan(F, p, mask, 32)
+    assert plan.autotune(32) == 1
+    chosen = plan.schedule
+    assert chosen in (0, 2)
+    with pytest.raises(F.FwrError) as e:
+        plan.set_schedule(1)
+    assert e.value.status == F.FWR_E_UNSUPPORTED
+    plan.close()
+    again = _plan(F, p, mask, 4)
+    assert again.schedule == chosen
+    slopes = I.random_slopes(4, 128, seed=31).astype(np.float32)
+    got = again.reconstruct(torch.from_numpy(slopes).cuda()).cpu().numpy().astype(np.float64)
+    for b in range(4):
+        assert _rel(got[b], O.reconstruct(slopes[b].astype(np.float64), mask, p)) <= 1e-5
+    again.close()
+
+
+@pytest.mark.parametrize("mp_schedule", [0, 2])
+def test_sinc_256_in_a_grouped_call(F, mp_schedule):
     """A multi-pass sinc plan beside an on-chip sinc plan and a Fried plan in one grouped call gives
-    the bits of the individual calls."""
-    _flush("[gpu] grouped call with the sinc multi-pass path")
+    the bits of the individual calls, with the multi-pass plans on either loop shape (beside other
+    items they run one launch per pass: the same bits)."""
+    _flush(f"[gpu] grouped call with the sinc multi-pass path, schedule {mp_schedule}")
     items = []
     for n, N, model in ((128, 256, "sinc"), (40, 80, "sinc"), (128, 256, "fried")):
         plan = F.Plan(n, N, I.pupil_mask(n), n_iter=3, periodic=True, max_batch=2, d=8.0 / n, model=model)
+        if N == 256:
+            plan.set_schedule(mp_schedule)
         x = torch.from_numpy(I.random_slopes(2, n, seed=n + N).astype(np.float32)).cuda()
         items.append((plan, x, torch.empty((2, n + 1, n + 1), device="cuda"), None, None))
     F.reconstruct_group(items)
