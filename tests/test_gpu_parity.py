@@ -370,6 +370,35 @@ def test_persistent_loop_watchdog(fwr):
     onchip.close()
 
 
+def test_persistent_loops_on_two_streams(fwr):
+    """Two plans on the persistent loop, enqueued on two streams at once (two launches that may share
+    the CUs; each waits only on its own items): the bits of each plan run alone."""
+    mask = I.pupil_mask(128)
+    p = O.Params(n_iter=10, periodic=True, **ELT)
+    _flush("[gpu] two persistent loops on two streams")
+    plans, xs, refs = [], [], []
+    for k in range(2):
+        plan = fwr.Plan(128, 256, mask, n_iter=10, periodic=True, gamma=p.gamma, noise_var=p.noise_var, r0=p.r0,
+                        L0=p.L0, d=p.d, max_batch=64)
+        plan.set_schedule(2)
+        x = torch.from_numpy(I.make_batch(I.ELT_128, 64, start=100 * k, dtype=np.float32)).cuda()
+        refs.append(plan.reconstruct(x).clone())
+        plans.append(plan)
+        xs.append(x)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    outs = [torch.empty_like(r) for r in refs]
+    for _ in range(3):
+        for plan, x, o, st in zip(plans, xs, outs, streams):
+            plan.set_stream(st.cuda_stream)
+            plan.reconstruct(x, o)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r)
+    for plan in plans:
+        plan.close()
+
+
 @pytest.mark.parametrize("B,n_iter,periodic", [(5, 20, True), (7, 2, True), (4, 3, False), (6, 1, True),
                                                (3, 5, False), (64, 10, True)])
 def test_persistent_loop_same_bits_as_launch_per_pass(fwr, B, n_iter, periodic):
