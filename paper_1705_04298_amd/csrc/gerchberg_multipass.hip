@@ -591,8 +591,6 @@ struct LoopArgs {
   int ri_b0, nri;         // row blocks of the last solve's inverse row FFTs (phi)
 };
 
-
-
 // item -> (column tile, fused row block or last-solve row block; step k, pair, tile / block index)
 struct LoopItem {
   int kind;  // 0 column tile, 1 fused row step block, 2 the last solve's inverse row block
@@ -603,7 +601,7 @@ struct LoopItem {
 // that every wait has the same slack, was measured slower: 0.753 against 0.727 ms per 128 frames)
 __device__ __forceinline__ LoopItem loop_item(int item, const LoopArgs &l, int n_iter) {
   const int per = R + l.nr;
-  const int ri0 = (n_iter - 1) * l.pairs * per + l.pairs * R;  // the last solve's items follow the last C step
+  const int ri0 = (n_iter - 1) * l.pairs * per + l.pairs * R;  // (the last solve's items follow)
   LoopItem it;
   if (item >= ri0) {
     it.kind = 2;
@@ -624,7 +622,7 @@ __device__ __forceinline__ LoopItem loop_item(int item, const LoopArgs &l, int n
 // (4 waves per SIMD: 3 workgroups per CU, as the LDS allows; letting the compiler use more registers
 // instead, without spills, left one workgroup per CU by the occupancy query: 1.11 ms per 128 frames)
 __global__ __launch_bounds__(FT, 4) void loop_kernel(MPArgs a, LoopArgs l) {
-  // one array, the twiddles first: their reads (base 16 r, offsets k) then fit the immediate offset
+  // one array, the twiddles first: their reads (base 17 r, offsets k) then fit the immediate offset
   // fields of the LDS instructions, with no address register per offset
   __shared__ float2 lds[TW_RK + (R + 2) * LP];
   float2 *const tw = lds, *const L = lds + TW_RK;
