@@ -417,7 +417,9 @@ hipError_t fourier_mp_run(const FSArgs &a0, bool extend, hipStream_t s) {
   const bool each = (a.flags & kFourierPeriodicEach) != 0;
   const int fix = ((a.flags & kFourierPeriodic) != 0 || (each && a.n_iter > 0)) ? 1 : 0;
   // launch shape 2: the loop's column passes and row steps in one persistent launch
-  const int lgrid = a.shape == 2 && !each && a.n_iter >= 2 ? fs_loop_grid() : 0;
+  // (the item indices are 32-bit: calls with more items than that run one launch per pass)
+  const long loop_items = (long)a.n_iter * a.B * 2 * R;
+  const int lgrid = a.shape == 2 && !each && a.n_iter >= 2 && loop_items < (1L << 30) ? fs_loop_grid() : 0;
   if (a.n_iter == 0) {
     hipLaunchKernelGGL(rows_kernel, grid, blk, 0, s, a, int(kInitStore), 0, 0);
   } else if (lgrid > 0) {

@@ -867,7 +867,9 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
   float2 *const spec2 = a.sy;
   const float2 *col_in = a.spec;
   // launch shape 2: the loop's column passes and fused row steps in one persistent launch
-  const int lgrid = a.col_shape == 2 && !each && a.n_iter >= 2 ? loop_grid() : 0;
+  // (the item indices are 32-bit: calls with more items than that run one launch per pass)
+  const long loop_items = (long)a.n_iter * pairs * (R + (wb1 - wb0 + 1) + NN / R);
+  const int lgrid = a.col_shape == 2 && !each && a.n_iter >= 2 && loop_items < (1L << 30) ? loop_grid() : 0;
   if (lgrid > 0) {
     const bool full_last = explicit_final && !eq5_sums;  // (as full_out of the last iteration below)
     LoopArgs l{};
@@ -883,7 +885,6 @@ hipError_t multipass_run(const MPArgs &a0, bool extend, hipStream_t s) {
     l.last_whi = full_last ? NN - 1 : rhi;
     l.ri_b0 = full_last ? 0 : rb0;  // the loop's last solve: inverse row FFTs of these row blocks
     l.nri = full_last ? NN / R : rb1 - rb0 + 1;
-    const long total = (long)(a.n_iter - 1) * pairs * (R + l.nr) + (long)pairs * R;
     // resident workgroups, at most half the items of one loop step (more only wait: measured)
     const long cap = std::min<long>(lgrid, (long)pairs * (R + l.nr) / 2);
     hipLaunchKernelGGL(loop_kernel, dim3((unsigned)std::max<long>(cap, 1)), dim3(FT), 0, s, a, l);
