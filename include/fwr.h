@@ -175,8 +175,9 @@ fwr_status fwr_plan_set_group(fwr_plan_t plan, int32_t frames_per_group);
  * take column tiles and row blocks from a counter and wait, through per-pair
  * counts in the plan's workspace, for the previous step of their own frame pair
  * only; the same arithmetic as 0, bit for bit).  Schedule 2 applies to calls with
- * at least two iterations and no per-iteration Eq. 5, and not to items of a
- * grouped call with other items, whose concurrent work needs the CUs its waiting
+ * at least two iterations and no per-iteration Eq. 5 (and fewer than 2^30 work
+ * items, about 40 per frame pair and iteration), and not to items of a grouped
+ * call with other items, whose concurrent work needs the CUs its waiting
  * workgroups would hold (those run as 0); a wait
  * that exceeds about a second gives up and writes the call's frames as NaN.
  * Schedule 2 is FWR_E_UNSUPPORTED on other plans.  Plans start from the schedule
