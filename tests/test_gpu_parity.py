@@ -399,6 +399,42 @@ def test_persistent_loops_on_two_streams(fwr):
         plan.close()
 
 
+def test_persistent_loop_in_a_graph(fwr):
+    """The persistent loop captured in a HIP graph and replayed several times, with eager work of
+    the same plan between the replays: every replay gives the eager bits (the start pass clears the
+    loop's counters as a kernel, so a replay starts from zero counts)."""
+    mask = I.pupil_mask(128)
+    p = O.Params(n_iter=6, periodic=True, **ELT)
+    _flush("[gpu] persistent loop in a graph")
+    plan = fwr.Plan(128, 256, mask, n_iter=6, periodic=True, gamma=p.gamma, noise_var=p.noise_var, r0=p.r0,
+                    L0=p.L0, d=p.d, max_batch=32)
+    plan.set_schedule(2)
+    x = torch.from_numpy(I.make_batch(I.ELT_128, 32, start=7, dtype=np.float32)).cuda()
+    x2 = torch.from_numpy(I.make_batch(I.ELT_128, 32, start=70, dtype=np.float32)).cuda()
+    ref = plan.reconstruct(x).clone()
+    ref2 = plan.reconstruct(x2).clone()
+    out = torch.empty_like(ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.set_stream()
+        plan.reconstruct(x, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.set_stream()
+        plan.reconstruct(x, out)
+    plan.set_stream()
+    for _ in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert torch.equal(plan.reconstruct(x2), ref2)  # (eager work of the same plan between replays)
+    plan.close()
+
+
 @pytest.mark.parametrize("B,n_iter,periodic", [(5, 20, True), (7, 2, True), (4, 3, False), (6, 1, True),
                                                (3, 5, False), (64, 10, True)])
 def test_persistent_loop_same_bits_as_launch_per_pass(fwr, B, n_iter, periodic):
