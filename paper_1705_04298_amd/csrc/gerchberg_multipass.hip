@@ -270,10 +270,11 @@ __global__ __launch_bounds__(THREADS) void row_fwd_kernel(MPArgs a, int mode_arg
 // the s_x field, unused on this path).  Outside the pupil the slopes are the model slopes of
 // the periodic phase, whose full-row (x) and full-column (y) sums vanish, so R_m and C_n are
 // these misfit sums alone.
+// (the block's y misfits reuse the LDS of its phi rows once every thread has read them: 36 KB of
+// LDS instead of 68 KB, four blocks per CU instead of two)
 __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
   __shared__ float2 ph[(R + 1) * NN];
   __shared__ float2 part[THREADS];
-  __shared__ float2 eyl[R * NN];
   const int t = threadIdx.x, rl = t >> 4, r = t & 15;
   const int pair = blockIdx.y, m0 = (blockIdx.x + b0) * R, m = m0 + rl;
   const float2 *P = a.phi + field(pair);
@@ -300,6 +301,7 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
   }
   __syncthreads();
   float2 acc = make_float2(0.f, 0.f);
+  float2 ey[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int nn = r + R * q, np = (nn + 1) & (NN - 1);
@@ -310,10 +312,12 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
     // (cleaned here, after the barrier, so that the loads above stay in flight across it)
     const float2 mxc = make_float2(clean(mx[q].x), clean(mx[q].y)), myc = make_float2(clean(my[q].x), clean(my[q].y));
     const float2 ex = inp[q] ? csub(mxc, gx) : make_float2(0.f, 0.f);
-    const float2 ey = inp[q] ? csub(myc, gy) : make_float2(0.f, 0.f);
+    ey[q] = inp[q] ? csub(myc, gy) : make_float2(0.f, 0.f);
     acc = cadd(acc, ex);
-    eyl[rl * NN + nn] = ey;
   }
+  __syncthreads();  // every read of the phi rows is done: their LDS takes the y misfits
+#pragma unroll
+  for (int q = 0; q < R; ++q) ph[rl * NN + r + R * q] = ey[q];
   part[t] = acc;
   __syncthreads();
   if (r == 0) {  // fixed-order row sum
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(THREADS) void eq5_kernel(MPArgs a, int b0) {
   }
   float2 cs = make_float2(0.f, 0.f);  // column t over the block's rows, fixed order
 #pragma unroll
-  for (int i = 0; i < R; ++i) cs = cadd(cs, eyl[i * NN + t]);
+  for (int i = 0; i < R; ++i) cs = cadd(cs, ph[i * NN + t]);
   (a.sx + field(pair))[(size_t)blockIdx.x * NN + t] = cs;
 }
 
