@@ -331,6 +331,22 @@ def test_elt128_persistent_loop(fwr, n_iter, periodic, each):
     check_reconstruct(fwr, slopes, mask, p, "elt-persistent", schedule=2)
 
 
+@pytest.mark.parametrize("n,periodic,n_iter", [(100, True, 7), (200, True, 5), (250, False, 4), (252, True, 3),
+                                              (64, True, 9)])
+def test_persistent_loop_other_windows(fwr, n, periodic, n_iter):
+    """The persistent loop on other lenslet counts of the 256 x 256 grid (window row blocks and the
+    stencil's reach of other sizes: 4 to 16 row blocks per step), random masks, against the oracle
+    and bit for bit against the launch-per-pass loop."""
+    mask = I.random_mask(n, seed=n + 17)
+    slopes = I.random_slopes(5, n, seed=n + 18)
+    p = O.Params(n_sub=n, n_grid=256, n_iter=n_iter, periodic=periodic, gamma=1.0, noise_var=0.01, r0=0.15,
+                 L0=25.0, d=39.0 / n)
+    check_reconstruct(fwr, slopes, mask, p, f"persistent n={n}", schedule=2)
+    a = run_case(fwr, slopes, mask, p, schedule=0)
+    b = run_case(fwr, slopes, mask, p, schedule=2)
+    assert np.array_equal(a, b)
+
+
 def test_persistent_loop_watchdog(fwr):
     """A wait limit of one poll makes the persistent loop give up as soon as an item finds its pair's
     previous step unfinished (forced from the host; every kernel still ends normally): the call's

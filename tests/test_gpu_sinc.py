@@ -305,6 +305,27 @@ def test_sinc_256_persistent_loop_same_bits(F, B, n_iter, periodic):
     plan.close()
 
 
+@pytest.mark.parametrize("n,periodic", [(100, True), (200, False)])
+def test_sinc_256_persistent_loop_other_windows(F, n, periodic):
+    """The lenslet-averaging persistent loop on other lenslet counts of the 256 x 256 grid, random
+    masks: against the oracle, and bit for bit against one launch per pass."""
+    _flush(f"[gpu] sinc 256 persistent n={n} periodic={periodic}")
+    mask = I.random_mask(n, seed=n + 3)
+    slopes = I.random_slopes(3, n, seed=n + 4).astype(np.float32)
+    p = O.Params(n_sub=n, n_grid=256, n_iter=5, periodic=periodic, d=39.0 / n, model="sinc")
+    plan = _plan(F, p, mask, 3)
+    x = torch.from_numpy(slopes).cuda()
+    plan.set_schedule(0)
+    ref = plan.reconstruct(x)
+    plan.set_schedule(2)
+    got = plan.reconstruct(x)
+    assert torch.equal(got, ref)
+    g = got.cpu().numpy().astype(np.float64)
+    for b in range(3):
+        assert _rel(g[b], O.reconstruct(slopes[b].astype(np.float64), mask, p)) <= 1e-5
+    plan.close()
+
+
 def test_sinc_256_persistent_loop_watchdog(F):
     """A one-poll wait limit makes the persistent loop give up (forced from the host): every frame
     NaN or every frame exact, and the next call with the default limit exact."""
