@@ -39,6 +39,11 @@ def test_host_side_validation_without_gpu():
     assert lib.fwr_plan(None, ctypes.byref(h)) == F.FWR_E_INVAL
     assert lib.fwr_destroy(None) == F.FWR_E_STATE
     assert F.fwr_reconstruct_learned(None, None, None, 0, 0, 0, 0, 0.0, 1) == F.FWR_E_STATE
+    # launch-shape calls on a NULL plan
+    assert lib.fwr_plan_set_schedule(None, 2) == F.FWR_E_STATE
+    assert lib.fwr_plan_set_wait_limit(None, 100) == F.FWR_E_STATE
+    assert lib.fwr_reconstruct_group(None, 0, None) == F.FWR_OK  # (no items: nothing to do)
+    assert lib.fwr_reconstruct_group(None, 1, None) == F.FWR_E_INVAL
     assert sorted(F.EXPORTED) == sorted(declared_functions())
 
 
